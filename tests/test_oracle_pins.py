@@ -1,0 +1,392 @@
+"""Pins of the CPU oracle against facts fixed by physics and mathematics.
+
+None of these re-types the oracle's formula: each compares it with an
+independent statement (a closed form, a symmetry, a limit, an identity or a
+different route to the same number), chosen so that a plausible slip -- a
+dropped term, a wrong sign or index, a transposed operand, a wrong helicity bit
+-- fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import qed_oracle as O
+from paper_2511_19456_amd import inputs
+
+F64 = torch.float64
+C128 = torch.complex128
+
+
+def rand_momenta(n, N, sqrt_s, seed):
+    u, _ = inputs.rambo_inputs(seed, n, N)
+    return O.momenta_from_uniforms(u, sqrt_s, n)
+
+
+# ---------------------------------------------------------------------------
+# Dirac algebra and external states
+# ---------------------------------------------------------------------------
+def test_clifford_algebra():
+    g = O.GAMMA
+    eta = torch.diag(torch.tensor([1.0, -1.0, -1.0, -1.0], dtype=C128))
+    for mu in range(4):
+        for nu in range(4):
+            ac = g[mu] @ g[nu] + g[nu] @ g[mu]
+            assert torch.allclose(ac, 2 * eta[mu, nu] * torch.eye(4, dtype=C128), atol=0)
+
+
+def test_spinors_and_polarisations():
+    mom = rand_momenta(3, 64, 10.0, 11)
+    p = mom[:, 2, :]
+    for s in (0, 1):
+        u = O.spinor_u(p, s)
+        ub = O.spinor_ubar(p, s)
+        # Dirac equation (pslash - m) u = 0
+        r = torch.einsum("nij,nj->ni", O.slash(p) - O.M_E * O.EYE4, u)
+        assert r.abs().max() < 1e-12
+        # normalisation ubar u = 2m
+        assert torch.allclose((ub * u).sum(-1).real, torch.full((64,), 2.0 * O.M_E, dtype=F64), atol=1e-12)
+    # completeness sum_s u ubar = pslash + m
+    comp = sum(torch.einsum("ni,nj->nij", O.spinor_u(p, s), O.spinor_ubar(p, s)) for s in (0, 1))
+    assert (comp - O.slash(p) - O.M_E * O.EYE4).abs().max() < 1e-12
+    for j in (3, 4, 5):
+        k = mom[:, j, :]
+        ex, ey = O.photon_pol(k, 0), O.photon_pol(k, 1)
+        assert O.mdot(ex, k).abs().max() < 1e-12 and O.mdot(ey, k).abs().max() < 1e-12
+        assert torch.allclose(O.mdot(ex, ex), -torch.ones(64, dtype=F64), atol=1e-14)
+        assert torch.allclose(O.mdot(ey, ey), -torch.ones(64, dtype=F64), atol=1e-14)
+        assert O.mdot(ex, ey).abs().max() < 1e-14
+        # (eps_x, eps_y, k-hat) is a right-handed triad
+        kh = k[:, 1:] / k[:, 1:].norm(dim=-1, keepdim=True)
+        assert (torch.cross(ex[:, 1:], ey[:, 1:], dim=-1) - kh).abs().max() < 1e-13
+
+
+def test_polarisation_along_z_axis_convention():
+    k = torch.tensor([[2.0, 0.0, 0.0, 2.0], [2.0, 0.0, 0.0, -2.0]], dtype=F64)
+    ex, ey = O.photon_pol(k, 0), O.photon_pol(k, 1)
+    assert torch.equal(ex[0], torch.tensor([0.0, 1.0, 0.0, 0.0], dtype=F64))
+    assert torch.equal(ey[0], torch.tensor([0.0, 0.0, 1.0, 0.0], dtype=F64))
+    assert torch.equal(ex[1], torch.tensor([0.0, -1.0, 0.0, 0.0], dtype=F64))
+
+
+# ---------------------------------------------------------------------------
+# P1/P2: Klein-Nishina (textbook closed forms, lab frame, m = 1)
+# ---------------------------------------------------------------------------
+def _kn_unpol(theta, omega=1.0):
+    wp = omega / (1.0 + omega * (1.0 - np.cos(theta)))
+    return 8.0 * (wp / omega + omega / wp - np.sin(theta) ** 2)
+
+
+def test_klein_nishina_worked_values():
+    th = np.array([0.0, math.pi / 2, math.pi])
+    m = inputs.compton_lab_angles(th, np.zeros(3))
+    got = O.m2(m, 1, "sum").numpy()
+    want = np.array([16.0, 12.0, 80.0 / 3.0])
+    assert np.max(np.abs(got / want - 1)) < 1e-13
+
+
+@pytest.mark.parametrize("omega", [1.0, 0.05, 7.3])
+def test_klein_nishina_random_angles(omega):
+    g = np.random.default_rng(5)
+    th = np.arccos(g.uniform(-1, 1, 400))
+    ph = g.uniform(0, 2 * math.pi, 400)
+    m = inputs.compton_lab_angles(th, ph, omega)
+    got = O.m2(m, 1, "sum").numpy()
+    assert np.max(np.abs(got / _kn_unpol(th, omega) - 1)) < 1e-13
+
+
+def test_klein_nishina_polarised():
+    """sum over electron spins at fixed photon polarisations:
+    2[w'/w + w/w' - 2 + 4 (eps.eps')^2]; worked theta=pi/2, phi=0: 1, 1, 1, 9."""
+    proc = O.Process(1)
+
+    def spin_summed(m_soa):
+        mom = O.soa_to_points(m_soa)
+        N = mom.shape[0]
+        out = {}
+        for lin in (0, 1):
+            for lout in (0, 1):
+                tot = torch.zeros(N, dtype=F64)
+                for s in (0, 1):
+                    for sp in (0, 1):
+                        h = s | (lin << 1) | (sp << 2) | (lout << 3)
+                        A = O.amplitudes(mom, torch.full((N, 1), h, dtype=torch.int64), proc)[:, 0]
+                        tot += A.abs() ** 2
+                out[(lin, lout)] = tot.numpy()
+        return out, mom
+
+    out, _ = spin_summed(inputs.compton_lab_angles(np.array([math.pi / 2]), np.array([0.0])))
+    for key, want in {(0, 0): 1.0, (0, 1): 1.0, (1, 0): 1.0, (1, 1): 9.0}.items():
+        assert abs(out[key][0] - want) < 1e-13 * want
+
+    g = np.random.default_rng(6)
+    th = np.arccos(g.uniform(-1, 1, 200))
+    ph = g.uniform(0, 2 * math.pi, 200)
+    out, mom = spin_summed(inputs.compton_lab_angles(th, ph))
+    wp = 1.0 / (1.0 + (1.0 - np.cos(th)))
+    for lin in (0, 1):
+        for lout in (0, 1):
+            e = O.photon_pol(mom[:, 1, :], lin)[:, 1:].numpy()
+            ep = O.photon_pol(mom[:, 3, :], lout)[:, 1:].numpy()
+            d = (e * ep).sum(-1)
+            want = 2.0 * (wp + 1.0 / wp - 2.0 + 4.0 * d * d)
+            assert np.max(np.abs(out[(lin, lout)] - want) / want.max()) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Per-spin values through a different route: traces with spin projectors
+# u ubar = (pslash + m)(1 + g5 sslash)/2, s = boosted rest-frame z axis.
+# ---------------------------------------------------------------------------
+def _gamma5():
+    g = O.GAMMA
+    return 1j * g[0] @ g[1] @ g[2] @ g[3]
+
+
+def _spin_vector(p, sign):
+    m = O.M_E
+    E = p[:, 0]
+    pz = p[:, 3]
+    s0 = pz / m
+    sv = torch.zeros_like(p[:, 1:])
+    sv[:, 2] = 1.0
+    sv = sv + (pz / (m * (E + m)))[:, None] * p[:, 1:]
+    return sign * torch.cat([s0[:, None], sv], dim=-1)
+
+
+def test_per_spin_values_by_trace():
+    n = 2
+    proc = O.Process(n)
+    mom = rand_momenta(n, 16, 6.0, 12)
+    N = mom.shape[0]
+    g5 = _gamma5()
+    p, pp = mom[:, 0], mom[:, 2]
+    # Dirac string Gamma (4x4) summed over orderings, at fixed photon polarisations
+    P = proc.n_photons
+    for lam in range(1 << P):
+        ws = []
+        ktil = []
+        bits = 0
+        for j, pi in enumerate(proc.photon_idx):
+            lj = (lam >> j) & 1
+            bits |= lj << pi
+            ws.append(O.slash(O.photon_pol(mom[:, pi], lj)))
+            ktil.append(proc.photon_sign[j] * mom[:, pi])
+        Gam = torch.zeros(N, 4, 4, dtype=C128)
+        import itertools
+        for sig in itertools.permutations(range(P)):
+            M = torch.eye(4, dtype=C128).expand(N, 4, 4)
+            Q = p.clone()
+            for i, a in enumerate(sig):
+                M = ws[a] @ M
+                if i < P - 1:
+                    Q = Q + ktil[a]
+                    M = (O.slash(Q) + O.M_E * O.EYE4) @ M / (O.mdot(Q, Q) - 1.0)[:, None, None]
+            Gam = Gam + M
+        Gbar = O.GAMMA[0] @ Gam.conj().transpose(-1, -2) @ O.GAMMA[0]
+        for s in (0, 1):
+            for sp in (0, 1):
+                rho_in = (O.slash(p) + O.M_E * O.EYE4) @ (O.EYE4 + g5 @ O.slash(_spin_vector(p, 1 - 2 * s))) / 2
+                rho_out = (O.slash(pp) + O.M_E * O.EYE4) @ (O.EYE4 + g5 @ O.slash(_spin_vector(pp, 1 - 2 * sp))) / 2
+                tr = torch.einsum("nii->n", rho_out @ Gam @ rho_in @ Gbar).real
+                h = bits | (s << proc.i_ein) | (sp << proc.i_eout)
+                A = O.amplitudes(mom, torch.full((N, 1), h, dtype=torch.int64), proc)[:, 0]
+                assert torch.allclose(A.abs() ** 2, tr, rtol=1e-11, atol=1e-13 * float(tr.abs().max()))
+
+
+# ---------------------------------------------------------------------------
+# P3: Ward identity -- replacing any photon's eps by its momentum gives 0
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_ward_identity(n):
+    proc = O.Process(n)
+    mom = rand_momenta(n, 8, 10.0, 20 + n)
+    N = mom.shape[0]
+    hel = O.all_helicities(N, proc)
+    K = hel.shape[1]
+    for j, pi in enumerate(proc.photon_idx):
+        kt = (proc.photon_sign[j] * mom[:, pi, :]).to(C128)[:, None, :].expand(N, K, 4)
+        A, absum = O.amplitudes(mom, hel, proc, photon_override={j: kt}, want_abs_terms=True)
+        assert float((A.abs() / absum).max()) < 1e-12
+        # and the un-replaced amplitude is not trivially small
+        A0, ab0 = O.amplitudes(mom, hel, proc, want_abs_terms=True)
+        assert float((A0.abs() / ab0).max()) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# P4: Lorentz invariance of the helicity sum
+# ---------------------------------------------------------------------------
+def _random_lorentz(seed):
+    g = np.random.default_rng(seed)
+    axis = g.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    eta = g.uniform(0, 2.0)
+    ch, sh = math.cosh(eta), math.sinh(eta)
+    B = np.eye(4)
+    B[0, 0] = ch
+    B[0, 1:] = sh * axis
+    B[1:, 0] = sh * axis
+    B[1:, 1:] = np.eye(3) + (ch - 1) * np.outer(axis, axis)
+    q, _ = np.linalg.qr(g.normal(size=(3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    R = np.eye(4)
+    R[1:, 1:] = q
+    return torch.tensor(R @ B, dtype=F64)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_lorentz_invariance_of_helicity_sum(n):
+    proc = O.Process(n)
+    mom = rand_momenta(n, 32, 8.0, 30 + n)
+    L = _random_lorentz(40 + n)
+    mom2 = torch.einsum("ij,npj->npi", L, mom)
+    a = O.m2_sum(mom, proc)
+    b = O.m2_sum(mom2, proc)
+    assert float(((a - b).abs() / a).max()) < 1e-11
+    # per-configuration values are frame dependent (basis fixed in the frame)
+    A = O.amplitudes(mom, O.all_helicities(32, proc), proc).abs()
+    B = O.amplitudes(mom2, O.all_helicities(32, proc), proc).abs()
+    assert float((A - B).abs().max() / A.max()) > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# P5: Bose symmetry of the outgoing photons; the (n+1)! diagram count
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 3])
+def test_bose_symmetry(n):
+    proc = O.Process(n)
+    mom = rand_momenta(n, 16, 9.0, 50 + n)
+    N = mom.shape[0]
+    hel = O.all_helicities(N, proc)
+    A = O.amplitudes(mom, hel, proc)
+    g = np.random.default_rng(60 + n)
+    perm = g.permutation(n)
+    while n > 1 and np.all(perm == np.arange(n)):
+        perm = g.permutation(n)
+    out_idx = list(range(3, 3 + n))
+    mom2 = mom.clone()
+    for a, b in enumerate(perm):
+        mom2[:, out_idx[a]] = mom[:, out_idx[b]]
+    # permute the helicity bits along with the momenta
+    h2 = hel.clone() & 0b111
+    for a, b in enumerate(perm):
+        h2 |= ((hel >> out_idx[b]) & 1) << out_idx[a]
+    A2 = O.amplitudes(mom2, h2, proc)
+    assert float(((A.abs() ** 2 - A2.abs() ** 2).abs() / (A.abs() ** 2).sum(-1, keepdim=True)).max()) < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_diagram_count(n):
+    assert O.Process(n).n_diagrams() == math.factorial(n + 1)
+    # the paper's orientation (n incoming photons, one outgoing) has the same count
+    assert O.Process(1, n_in=n).n_diagrams() == math.factorial(n + 1)
+
+
+# ---------------------------------------------------------------------------
+# P10: soft-photon limit, n photons -> eikonal factor x (n-1) photons
+# ---------------------------------------------------------------------------
+def _boost_to(P, mom):
+    """Boost momenta mom[N,k,4] from the rest frame of mass sqrt(P^2) to total momentum P[N,4]."""
+    M = torch.sqrt(O.mdot(P, P))
+    b = P[:, 1:] / P[:, 0:1]
+    gam = P[:, 0] / M
+    bp = (b[:, None, :] * mom[..., 1:]).sum(-1)
+    b2 = (b * b).sum(-1)
+    coef = torch.where(b2 > 0, (gam - 1) / torch.where(b2 > 0, b2, torch.ones_like(b2)), torch.zeros_like(b2))
+    E = gam[:, None] * (mom[..., 0] + bp)
+    pv = mom[..., 1:] + (coef[:, None] * bp)[..., None] * b[:, None, :] + (gam[:, None] * mom[..., 0])[..., None] * b[:, None, :]
+    return torch.cat([E[..., None], pv], dim=-1)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_soft_photon_limit(n):
+    sqrt_s = 6.0
+    Nh = 8
+    u, _ = inputs.rambo_inputs(70 + n, n - 1, Nh)
+    hard0 = O.momenta_from_uniforms(u, sqrt_s, n - 1)
+    g = np.random.default_rng(80 + n)
+    dirs = torch.tensor(g.normal(size=(Nh, 3)), dtype=F64)
+    dirs = dirs / dirs.norm(dim=-1, keepdim=True)
+    ratios = []
+    for lam in (1e-3, 1e-4):
+        q = torch.cat([torch.full((Nh, 1), lam, dtype=F64), lam * dirs], dim=-1)
+        Ptot = hard0[:, 0] + hard0[:, 1]
+        Ph = Ptot - q
+        Mh = float(torch.sqrt(O.mdot(Ph, Ph)).min())
+        # hard final state at invariant mass sqrt(Ph^2) from the same uniforms, boosted
+        fins = []
+        for i in range(Nh):
+            mh = float(torch.sqrt(O.mdot(Ph[i], Ph[i])))
+            f = O.rambo(torch.as_tensor(u[:, i:i + 1]), mh, [O.M_E] + [0.0] * (n - 1))
+            fins.append(_boost_to(Ph[i:i + 1], f))
+        fin = torch.cat(fins, 0)
+        mom = torch.cat([hard0[:, 0:1], hard0[:, 1:2], fin[:, 0:1], fin[:, 1:], q[:, None, :]], dim=1)
+        big = O.m2_sum(mom, O.Process(n))
+        small = O.m2_sum(hard0, O.Process(n - 1))
+        p, pp = hard0[:, 0], hard0[:, 2]
+        pq, ppq = O.mdot(p, q), O.mdot(pp, q)
+        eik = 2 * O.mdot(p, pp) / (pq * ppq) - 1.0 / pq ** 2 - 1.0 / ppq ** 2
+        ratios.append((big / (eik * small) - 1).abs())
+        assert Mh > 0
+    # the deviation is O(lambda): about 10x smaller at 1e-4 than at 1e-3
+    assert float(ratios[1].max()) < 1e-3
+    assert float(ratios[1].max()) < 0.15 * float(ratios[0].max())
+
+
+# ---------------------------------------------------------------------------
+# RAMBO: conservation, mass shells, two-body closed form, flatness
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,sqrt_s", [(1, 5.0), (3, 10.0), (5, 20.0)])
+def test_rambo_conservation_and_shells(n, sqrt_s):
+    mom = rand_momenta(n, 500, sqrt_s, 90 + n)
+    tot_in = mom[:, 0] + mom[:, 1]
+    tot_out = mom[:, 2:].sum(1)
+    assert float((tot_in - tot_out).abs().max()) < 1e-12 * sqrt_s
+    assert torch.allclose(tot_in[:, 0], torch.full((500,), sqrt_s, dtype=F64), atol=1e-13 * sqrt_s)
+    m2 = O.mdot(mom, mom)
+    assert float((m2[:, 0] - 1).abs().max()) < 1e-12 and float((m2[:, 2] - 1).abs().max()) < 1e-12
+    assert float(m2[:, 1].abs().max()) < 1e-12 * sqrt_s ** 2
+    assert float(m2[:, 3:].abs().max()) < 1e-12 * sqrt_s ** 2
+
+
+def test_rambo_two_body_closed_form():
+    sqrt_s = 7.0
+    mom = rand_momenta(1, 300, sqrt_s, 95)
+    want = (sqrt_s ** 2 - 1.0) / (2 * sqrt_s)
+    assert torch.allclose(mom[:, 3, 1:].norm(dim=-1), torch.full((300,), want, dtype=F64), rtol=1e-13)
+    assert torch.allclose(mom[:, 3, 0], torch.full((300,), want, dtype=F64), rtol=1e-13)
+
+
+def test_rambo_massless_three_body_is_flat():
+    """Flat massless 3-body phase space: E1 has CDF (2 E1 / sqrt s)^2; cos(theta) uniform."""
+    sqrt_s = 3.0
+    u = torch.as_tensor(inputs.uniforms(96, 12, 40000), dtype=F64)
+    f = O.rambo(u, sqrt_s, [0.0, 0.0, 0.0])
+    e1 = np.sort(f[:, 0, 0].numpy())
+    cdf_model = (2 * e1 / sqrt_s) ** 2
+    emp = np.arange(1, e1.size + 1) / e1.size
+    assert np.max(np.abs(emp - cdf_model)) < 0.012  # KS at 40k samples
+    c = np.sort((f[:, 1, 3] / f[:, 1, 0]).numpy())
+    assert np.max(np.abs(np.arange(1, c.size + 1) / c.size - (c + 1) / 2)) < 0.012
+
+
+# ---------------------------------------------------------------------------
+# P12 (oracle side): gradient against central finite differences
+# ---------------------------------------------------------------------------
+def test_gradient_matches_central_differences():
+    n, sqrt_s = 2, 8.0
+    u, _ = inputs.rambo_inputs(97, n, 6)
+    u = np.clip(u, 1e-3, 1 - 1e-3)
+    val, grad = O.logm2_and_grad(u, sqrt_s, n)
+    h = 1e-6
+    fd = np.zeros_like(u)
+    for d in range(u.shape[0]):
+        up, um = u.copy(), u.copy()
+        up[d] += h
+        um[d] -= h
+        fd[d] = ((O.logm2_value(up, sqrt_s, n) - O.logm2_value(um, sqrt_s, n)) / (2 * h)).numpy()
+    g = grad.numpy()
+    err = np.linalg.norm(g - fd, axis=0) / np.linalg.norm(g, axis=0)
+    assert err.max() < 1e-6
+    assert torch.allclose(val, O.logm2_value(u, sqrt_s, n), rtol=1e-14)

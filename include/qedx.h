@@ -1,0 +1,196 @@
+/* qedx.h -- C ABI of the batched tree-level QED |M|^2 library (MI355X, gfx950).
+ *
+ * Process: e-(p) gamma(k) -> e-(p') gamma(k'_1) ... gamma(k'_n), n = 1..6, one
+ * electron line, all (n+1)! tree diagrams (Sec. III-A of the paper: the number
+ * of orderings in which the photons bind to the electron).  The amplitude is
+ * the paper's computation graph (Sec. II-B: base states U, vertices V,
+ * propagators S1, joins S2, diagram Sum) after node reduction (App. C),
+ * compiled into one straight-line GPU kernel per process variant.
+ *
+ * Conventions shared by every entry point
+ *  - Units hbar = c = 1, electron mass m = 1, metric (+,-,-,-).
+ *  - Particle order: [e-_in, gamma_in, e-_out, gamma_out_1..n].
+ *  - Momenta are float64 SoA, [4*(n+3)][N] row-major: row 4*i + mu holds
+ *    component mu (E, px, py, pz) of particle i for all N points.  The caller
+ *    guarantees on-shell momenta and momentum conservation.
+ *  - Reported value: reduced |M|^2 = sum over the selected spin/polarisation
+ *    configurations of |A|^2 with the coupling e and the overall phase of
+ *    (-ie)^(n+1) i^n dropped; the physical value is (4 pi alpha)^(n+1) times it.
+ *  - Helicity code (uint32): bit i belongs to particle i; 0 = spin +1/2 (rest
+ *    frame z spin boosted to p) or linear polarisation x; 1 = spin -1/2 or
+ *    polarisation y; x = (cos t cos f, cos t sin f, -sin t), y = (-sin f, cos f, 0)
+ *    in the frame of the given momenta, k-hat = (sin t cos f, sin t sin f, cos t).
+ *  - Every device pointer must be a device allocation on the current HIP
+ *    device, contiguous, 8-byte aligned (4-byte for helicity codes), and must
+ *    not alias an output.  The caller owns all device buffers; the library
+ *    owns process and plan handles.
+ *  - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream)
+ *    and return without synchronising.  Launch failures return QED_ERR_HIP.
+ *  - On any error the function returns a nonzero status, writes nothing to
+ *    the outputs, and qed_last_error() returns a message (thread-local).
+ *  - N == 0 is a valid no-op.  No entry point allocates device memory except
+ *    qed_batch_plan_create (its tile table).
+ */
+#ifndef QEDX_H
+#define QEDX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qed_process qed_process;       /* immutable after create */
+typedef struct qed_batch_plan qed_batch_plan; /* segment table + captured graph */
+
+typedef enum {
+  QED_OK = 0,
+  QED_ERR_INVALID_ARG = 1,
+  QED_ERR_UNSUPPORTED = 2,
+  QED_ERR_HIP = 3,
+  QED_ERR_COMPILE = 4,
+  QED_ERR_OOM = 5
+} qed_status;
+
+/* QED_HEL_SUM: sum over all 2^(n+3) spin/polarisation configurations.
+ * QED_HEL_PER_POINT: one configuration per point, from a helicity array. */
+typedef enum { QED_HEL_SUM = 0, QED_HEL_PER_POINT = 1 } qed_hel_mode;
+
+/* QED_FP64: every step in float64.
+ * QED_FP32C: currents, vertices, propagator numerators and diagram values in
+ * float32 with compensated (TwoSum) accumulation of the diagram sum;
+ * momenta, propagator momenta and denominators, |A|^2 and the helicity sum in
+ * float64.  Relative error against float64 is bounded by 1e-4 on the stated
+ * workloads (measured, not guaranteed for arbitrary points). */
+typedef enum { QED_FP64 = 0, QED_FP32C = 1 } qed_precision;
+
+/* Kernel shape knobs (all zero = library default for the process).
+ * lane_bits:  helicity bits spread over lanes (2^lane_bits lanes per point),
+ *             given as a mask over particle bits; SUM mode only.
+ * loop_bits:  helicity bits enumerated by a run-time loop; SUM mode only.
+ * The remaining bits are enumerated inside the graph.  block = threads per
+ * workgroup (multiple of 64, <= 1024).  split = photons on the e-_in side
+ * of every join (1..n). */
+typedef struct {
+  uint32_t lane_bits;
+  uint32_t loop_bits;
+  int32_t block;
+  int32_t split;
+  int32_t min_waves;    /* minimum waves per SIMD the compiler must allow (0 = free) */
+  int32_t order;        /* emission schedule flags (0 = library default) */
+  int32_t use_defaults; /* nonzero: ignore the fields above */
+} qed_variant;
+
+typedef struct {
+  int32_t n, mode, precision;
+  int64_t nodes_unreduced;   /* CDAG size before node reduction, in-lane graph */
+  int64_t nodes_reduced;     /* after reduction and join expansion */
+  int64_t n_V, n_S1, n_dot, n_prop;
+  double flops_per_point;    /* algorithmic FLOPs per point (add/mul 1, fma 2) */
+  int32_t lanes_per_point, block;
+  int32_t vgpr, agpr, sgpr, scratch_bytes, lds_bytes; /* from the code object */
+  double create_ms_build, create_ms_reduce, create_ms_emit, create_ms_compile, create_ms_load;
+  int32_t cache_hit;         /* 1 if the code object came from the cache */
+  char kernel_tag[160];
+} qed_info;
+
+/* Build the graph for n outgoing photons (1..6), reduce it, emit and compile
+ * (or load from the code-object cache) the kernel.  Loads the module on the
+ * current device.  `variant` may be NULL.  Returns QED_ERR_COMPILE if the
+ * generated code does not compile, QED_ERR_UNSUPPORTED for n outside 1..6
+ * or a mode/precision not built for that n. */
+qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
+                              qed_process** out);
+qed_status qed_process_destroy(qed_process* p);
+qed_status qed_process_info(const qed_process* p, qed_info* out);
+
+/* |M|^2 for N points (Sec. II-B: the graph takes all four-momenta and returns
+ * one real number per point).
+ * momenta: device, float64 [4(n+3)][N]; hel: device uint32 [N] in PER_POINT
+ * mode and NULL in SUM mode; out: device float64 [N].
+ * INVALID_ARG if N < 0, a required pointer is NULL while N > 0, or hel does not
+ * match the mode. */
+qed_status qed_eval(const qed_process* p, const double* momenta, const uint32_t* hel, int64_t N, double* out,
+                    void* stream);
+
+/* RAMBO phase space (Kleiss, Stirling, Ellis 1986) for this process at
+ * centre-of-mass energy sqrt_s > m: writes full momenta [4(n+3)][N] with the
+ * incoming pair in its CM frame (photon along +z) and the final state
+ * [e-_out (mass 1), n photons] from uniforms [4(n+1)][N] in (0,1) (rows
+ * 4j..4j+3 belong to final-state particle j).  INVALID_ARG if sqrt_s <= 1. */
+qed_status qed_rambo(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N, double* momenta_out,
+                     void* stream);
+
+/* log|M|^2 (SUM mode processes) and its gradient with respect to the RAMBO
+ * uniforms: out_logm2 [N], out_grad [4(n+1)][N] (row = uniform index), both
+ * float64 device buffers.  Forward RAMBO, forward graph, adjoint graph and
+ * adjoint RAMBO run in one kernel; nothing is stored between passes.
+ * `hel` must be NULL.  UNSUPPORTED for PER_POINT or FP32C processes. */
+qed_status qed_eval_grad(const qed_process* p, const double* uniforms, double sqrt_s, const uint32_t* hel,
+                         int64_t N, double* out_logm2, double* out_grad, void* stream);
+
+/* Mixed-process batches: segments of different processes evaluated by one
+ * persistent kernel launch (captured in a HIP graph at plan creation).
+ * All processes of one plan must share the precision and be PER_POINT. */
+typedef struct {
+  const qed_process* proc;
+  const double* momenta; /* device [4(n+3)][N] */
+  const uint32_t* hel;   /* device [N] */
+  int64_t N;
+  double* out;           /* device [N] */
+} qed_segment;
+
+/* tile_points = points per work tile (0 = autotuned default).  The plan
+ * copies the segment table to the device and instantiates the graph; the
+ * segment buffers must stay valid while the plan is launched. */
+qed_status qed_batch_plan_create(const qed_segment* segs, int nseg, int tile_points, qed_batch_plan** out);
+qed_status qed_batch_launch(qed_batch_plan* plan, void* stream);
+qed_status qed_batch_plan_destroy(qed_batch_plan* plan);
+
+/* Last error message of the calling thread ("" if none). */
+const char* qed_last_error(void);
+
+/* Code-object cache directory in use (QEDX_CACHE_DIR or the package default). */
+const char* qed_cache_dir(void);
+
+/* Host-side graph tools (no GPU needed), for inspection and tests.
+ * qed_graph_counts: node counts of the generated graph for n, enumerated
+ * helicity bits `enum_mask` and join split `split`: reduced = 0 gives the
+ * paper's unreduced form (one chain per diagram, S2 joins); reduced = 1 the
+ * node-reduced, join-expanded form.  counts[10] = total, data, compute, U, V,
+ * S1, S2, Dot, Sum, HelSum. */
+qed_status qed_graph_counts(int n, int n_in, uint32_t enum_mask, int split, int reduced, int64_t* counts);
+/* Host interpreter of the graph (float64), per point: value of the exit node
+ * (sum over enum_mask configurations of |A|^2) with the other bits from hel.
+ * reduced as above; mom is host [N][4(n_in+n+2)] (point-major); out host [N]. */
+qed_status qed_graph_interpret(int n, int n_in, uint32_t enum_mask, int split, int reduced, const double* mom,
+                               const uint32_t* hel, int64_t N, double* out);
+/* Canonical structure hash text of the reduced graph reached by (a) the
+ * one-pass fixpoint and (b) single reductions in a random order seeded by
+ * `seed`; writes at most buflen bytes of each.  Returns the number of single
+ * reductions in *steps. */
+qed_status qed_graph_reduction_check(int n, int n_in, uint32_t enum_mask, int split, uint64_t seed, char* canon_a,
+                                     char* canon_b, int64_t buflen, int64_t* steps);
+/* Generated HIP source of the eval kernel for a variant (for inspection and
+ * for prebuilding the cache); writes at most buflen bytes, returns the full
+ * length in *len. */
+qed_status qed_emit_source(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant, char* buf,
+                           int64_t buflen, int64_t* len);
+
+/* C(DAG) and D(DAG) of the graph (App. B graph metrics): compute effort in
+ * FLOPs (add/mul 1, fma 2, div/sqrt 1, per point) and data transfer in bytes,
+ * with float32 value sizes if fp32 != 0. */
+qed_status qed_graph_metrics(int n, int n_in, uint32_t enum_mask, int split, int reduced, int fp32,
+                             double* c_dag, double* d_dag);
+/* Emit and compile the kernels of one process variant into the code-object
+ * cache without touching the GPU (ahead-of-time build).  with_aux = 1 also
+ * builds the RAMBO/gradient module.  *compile_ms receives the compile time
+ * (0 on a cache hit). */
+qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant, int with_aux,
+                        double* compile_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QEDX_H */

@@ -1,0 +1,126 @@
+"""Build the qedx native library and prebuild its kernel cache.
+
+Steps
+1. Embed the device headers (qedx_device.h, qedx_rambo.h) as a raw string
+   literal so generated kernels are self-contained translation units.
+2. Compile the host library libqedx.so (graph builder, reducer, emitter,
+   runtime) with the host C++ compiler against the HIP runtime.
+3. Emit and compile (hipcc --genco, gfx950) the kernels of the default process
+   variants into the code-object cache next to the library, in parallel.
+   Cache entries are keyed by the hash of source + flags, so unchanged kernels
+   are not recompiled.
+
+Run as ``python -m paper_2511_19456_amd.build_ext [--no-kernels] [--jobs J]``.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import ctypes
+import os
+import subprocess
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libqedx.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+HOST_SOURCES = ["qedx_dag.cpp", "qedx_emit.cpp", "qedx_kernels.cpp", "qedx_runtime.cpp", "qedx_batch.cpp"]
+DEVICE_HEADERS = ["qedx_device.h", "qedx_rambo.h"]
+
+
+def embed_headers() -> None:
+    parts = []
+    for h in DEVICE_HEADERS:
+        txt = open(os.path.join(CSRC, h)).read().replace("#pragma once\n", "")
+        parts.append(txt)
+    body = "\n".join(parts)
+    assert ")QEDXHDR\"" not in body
+    out = 'R"QEDXHDR(' + body + ')QEDXHDR"\n'
+    path = os.path.join(CSRC, "qedx_device_embed.inc")
+    if not os.path.exists(path) or open(path).read() != out:
+        with open(path, "w") as f:
+            f.write(out)
+
+
+def build_library(verbose: bool = False) -> None:
+    embed_headers()
+    objs = []
+    cmds = []
+    for s in HOST_SOURCES:
+        o = os.path.join(CSRC, "_build", s.replace(".cpp", ".o"))
+        os.makedirs(os.path.dirname(o), exist_ok=True)
+        objs.append(o)
+        cmds.append(["g++", "-std=c++17", "-O2", "-fPIC", "-Wall", "-Wno-unused-function",
+                     "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-c", os.path.join(CSRC, s), "-o", o])
+    with cf.ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        futs = [ex.submit(subprocess.run, c, capture_output=True, text=True) for c in cmds]
+        for c, f in zip(cmds, futs):
+            r = f.result()
+            if r.returncode != 0:
+                raise RuntimeError("compile failed: " + " ".join(c) + "\n" + r.stderr)
+            if verbose and r.stderr:
+                print(r.stderr, file=sys.stderr)
+    tmp = LIB + ".tmp"
+    link = ["g++", "-shared", "-o", tmp] + objs + [f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib"]
+    r = subprocess.run(link, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: " + r.stderr)
+    os.replace(tmp, LIB)
+
+
+class QedVariant(ctypes.Structure):
+    _fields_ = [("lane_bits", ctypes.c_uint32), ("loop_bits", ctypes.c_uint32), ("block", ctypes.c_int32),
+                ("split", ctypes.c_int32), ("min_waves", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("use_defaults", ctypes.c_int32)]
+
+
+# (n, mode, precision) built ahead of time: SUM 0 / PER_POINT 1; FP64 0 / FP32C 1
+DEFAULT_KERNELS = [
+    (1, 0, 0), (2, 0, 0), (3, 0, 0),
+    (1, 1, 0), (2, 1, 0), (3, 1, 0), (5, 1, 0),
+]
+
+
+def prebuild_kernels(kernels=DEFAULT_KERNELS, jobs: int = 8, verbose: bool = True) -> dict:
+    lib = ctypes.CDLL(LIB)
+    lib.qed_prebuild.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_double)]
+    lib.qed_prebuild.restype = ctypes.c_int
+    lib.qed_last_error.restype = ctypes.c_char_p
+
+    def one(k):
+        n, mode, prec = k
+        ms = ctypes.c_double(0.0)
+        t = time.time()
+        rc = lib.qed_prebuild(n, mode, prec, None, 1, ctypes.byref(ms))
+        err = lib.qed_last_error().decode() if rc else ""
+        return k, rc, ms.value, time.time() - t, err
+
+    out = {}
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for k, rc, ms, wall, err in ex.map(one, kernels):
+            out[k] = (rc, ms)
+            if verbose:
+                print(f"[qedx build] kernel n={k[0]} mode={k[1]} prec={k[2]}: rc={rc} compile={ms / 1e3:.1f}s",
+                      flush=True)
+            if rc:
+                raise RuntimeError(f"kernel prebuild failed for {k}: {err}")
+    return out
+
+
+def main(argv=None) -> None:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--no-kernels", action="store_true")
+    ap.add_argument("--jobs", type=int, default=8)
+    a = ap.parse_args(argv)
+    build_library()
+    if not a.no_kernels:
+        prebuild_kernels(jobs=a.jobs)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,271 @@
+// qedx_device.h -- per-lane building blocks of the QED matrix-element kernels.
+//
+// These are the compute tasks of the paper's QED computation graph (Sec. II-B:
+// base_state U, vertex V, propagator S1, join S2 and Sum), written for one
+// phase-space point per lane.  Generated kernels include this header verbatim
+// and call these functions once per graph node; the host-side graph
+// interpreter uses the same functions on the CPU.
+//
+// Representation.  Chiral (Weyl) basis, gamma^mu = [[0, sigma^mu], [sigmabar^mu, 0]]
+// with sigma = (1, sigma_vec), sigmabar = (1, -sigma_vec), so that
+//   a-slash = [[0, a0 - a.sigma], [a0 + a.sigma, 0]].
+// A fermion current from the incoming-electron side is a column 4-spinor
+// (L0, L1, R0, R1); one from the outgoing-electron side is a row spinor
+// (ubar-side, same component order).  The physical states are the Dirac-basis
+// ones -- rest-frame z spin boosted to p -- mapped by the unitary
+// (1/sqrt2)[[1,-1],[1,1]], which leaves every amplitude unchanged.
+//
+// Polarisation vectors are linear (x, y), real, with eps^0 = 0 in the frame
+// of the input momenta, so eps-slash = [[0, -E], [E, 0]] with
+// E = eps_vec . sigma = [[e3, e1 - i e2], [e1 + i e2, -e3]].
+//
+// Propagator S(Q) = (Q-slash + m) / (Q^2 - m^2) (Sec. I-D, i and i*epsilon
+// dropped).  Callers pass Q/D and m/D precomputed in double precision:
+//   qm = (Q0 - Q3)/D, qp = (Q0 + Q3)/D, q1 = Q1/D, q2 = Q2/D, mm = m/D.
+//
+// FLOP counts (add/mul = 1, fma = 2) are stated per function; the host cost
+// model uses the same numbers.
+#pragma once
+
+#ifndef QEDX_HD
+#define QEDX_HD __host__ __device__ inline
+#endif
+
+namespace qx {
+
+template <class T> struct cx { T r, i; };
+template <class T> struct sp4 { cx<T> c[4]; };          // L0 L1 R0 R1
+template <class T> struct pol3 { T e1, e2, e3; };        // eps_vec, eps^0 = 0
+template <class T> struct propq { T qm, qp, q1, q2, mm; };
+
+// ---------------------------------------------------------------------------
+// 2x2 blocks.  E x and x E for E = [[e3, e1 - i e2], [e1 + i e2, -e3]].
+// y0 = e3 x0 + (e1 - i e2) x1 ; y1 = (e1 + i e2) x0 - e3 x1.     20 FLOPs
+// With e3 == 0 (the y polarisation) use the *_y forms.            12 FLOPs
+// ---------------------------------------------------------------------------
+template <class T>
+QEDX_HD void Ex(const pol3<T>& e, const cx<T>& x0, const cx<T>& x1, T s, cx<T>& y0, cx<T>& y1) {
+  // s = +1 or -1 folds a sign into the result (free: source modifiers)
+  y0.r = s * (e.e3 * x0.r + e.e1 * x1.r + e.e2 * x1.i);
+  y0.i = s * (e.e3 * x0.i + e.e1 * x1.i - e.e2 * x1.r);
+  y1.r = s * (e.e1 * x0.r - e.e2 * x0.i - e.e3 * x1.r);
+  y1.i = s * (e.e1 * x0.i + e.e2 * x0.r - e.e3 * x1.i);
+}
+template <class T>
+QEDX_HD void Ex_y(const pol3<T>& e, const cx<T>& x0, const cx<T>& x1, T s, cx<T>& y0, cx<T>& y1) {
+  y0.r = s * (e.e1 * x1.r + e.e2 * x1.i);
+  y0.i = s * (e.e1 * x1.i - e.e2 * x1.r);
+  y1.r = s * (e.e1 * x0.r - e.e2 * x0.i);
+  y1.i = s * (e.e1 * x0.i + e.e2 * x0.r);
+}
+// row x times E: (x0 e3 + x1 (e1 + i e2), x0 (e1 - i e2) - x1 e3)
+template <class T>
+QEDX_HD void xE(const pol3<T>& e, const cx<T>& x0, const cx<T>& x1, T s, cx<T>& y0, cx<T>& y1) {
+  y0.r = s * (e.e3 * x0.r + e.e1 * x1.r - e.e2 * x1.i);
+  y0.i = s * (e.e3 * x0.i + e.e1 * x1.i + e.e2 * x1.r);
+  y1.r = s * (e.e1 * x0.r + e.e2 * x0.i - e.e3 * x1.r);
+  y1.i = s * (e.e1 * x0.i - e.e2 * x0.r - e.e3 * x1.i);
+}
+template <class T>
+QEDX_HD void xE_y(const pol3<T>& e, const cx<T>& x0, const cx<T>& x1, T s, cx<T>& y0, cx<T>& y1) {
+  y0.r = s * (e.e1 * x1.r - e.e2 * x1.i);
+  y0.i = s * (e.e1 * x1.i + e.e2 * x1.r);
+  y1.r = s * (e.e1 * x0.r + e.e2 * x0.i);
+  y1.i = s * (e.e1 * x0.i - e.e2 * x0.r);
+}
+
+// ---------------------------------------------------------------------------
+// V: vertex.  Left current:  J' = eps-slash J   = (-E R, E L).       40 FLOPs
+//             Right current: J'bar = Jbar eps-slash = (b E, -a E).    40 FLOPs
+// ("_y" variants for e3 == 0: 24 FLOPs.)
+// ---------------------------------------------------------------------------
+template <class T> QEDX_HD sp4<T> vL(const sp4<T>& J, const pol3<T>& e) {
+  sp4<T> o;
+  Ex<T>(e, J.c[2], J.c[3], T(-1), o.c[0], o.c[1]);
+  Ex<T>(e, J.c[0], J.c[1], T(1), o.c[2], o.c[3]);
+  return o;
+}
+template <class T> QEDX_HD sp4<T> vL_y(const sp4<T>& J, const pol3<T>& e) {
+  sp4<T> o;
+  Ex_y<T>(e, J.c[2], J.c[3], T(-1), o.c[0], o.c[1]);
+  Ex_y<T>(e, J.c[0], J.c[1], T(1), o.c[2], o.c[3]);
+  return o;
+}
+template <class T> QEDX_HD sp4<T> vR(const sp4<T>& J, const pol3<T>& e) {
+  sp4<T> o;
+  xE<T>(e, J.c[2], J.c[3], T(1), o.c[0], o.c[1]);
+  xE<T>(e, J.c[0], J.c[1], T(-1), o.c[2], o.c[3]);
+  return o;
+}
+template <class T> QEDX_HD sp4<T> vR_y(const sp4<T>& J, const pol3<T>& e) {
+  sp4<T> o;
+  xE_y<T>(e, J.c[2], J.c[3], T(1), o.c[0], o.c[1]);
+  xE_y<T>(e, J.c[0], J.c[1], T(-1), o.c[2], o.c[3]);
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// S1: propagator.  Left:  (Q-slash + m) J / D = (mm L + Qs R, Qb L + mm R)
+//                  Right: Jbar (Q-slash + m) / D = (mm a + b Qb, a Qs + mm b)
+// Qs = Q.sigma/D = [[qm, -q1 + i q2], [-q1 - i q2, qp]],
+// Qb = Q.sigmabar/D = [[qp, q1 - i q2], [q1 + i q2, qm]].        56 FLOPs each
+// ---------------------------------------------------------------------------
+template <class T> QEDX_HD sp4<T> sL(const sp4<T>& J, const propq<T>& q) {
+  const cx<T>&L0 = J.c[0], &L1 = J.c[1], &R0 = J.c[2], &R1 = J.c[3];
+  sp4<T> o;
+  o.c[0].r = q.mm * L0.r + q.qm * R0.r - q.q1 * R1.r - q.q2 * R1.i;
+  o.c[0].i = q.mm * L0.i + q.qm * R0.i - q.q1 * R1.i + q.q2 * R1.r;
+  o.c[1].r = q.mm * L1.r - q.q1 * R0.r + q.q2 * R0.i + q.qp * R1.r;
+  o.c[1].i = q.mm * L1.i - q.q1 * R0.i - q.q2 * R0.r + q.qp * R1.i;
+  o.c[2].r = q.mm * R0.r + q.qp * L0.r + q.q1 * L1.r + q.q2 * L1.i;
+  o.c[2].i = q.mm * R0.i + q.qp * L0.i + q.q1 * L1.i - q.q2 * L1.r;
+  o.c[3].r = q.mm * R1.r + q.q1 * L0.r - q.q2 * L0.i + q.qm * L1.r;
+  o.c[3].i = q.mm * R1.i + q.q1 * L0.i + q.q2 * L0.r + q.qm * L1.i;
+  return o;
+}
+template <class T> QEDX_HD sp4<T> sR(const sp4<T>& J, const propq<T>& q) {
+  const cx<T>&a0 = J.c[0], &a1 = J.c[1], &b0 = J.c[2], &b1 = J.c[3];
+  sp4<T> o;
+  // (mm a + b Qb): b Qb = (b0 qp + b1 (q1 + i q2), b0 (q1 - i q2) + b1 qm)
+  o.c[0].r = q.mm * a0.r + q.qp * b0.r + q.q1 * b1.r - q.q2 * b1.i;
+  o.c[0].i = q.mm * a0.i + q.qp * b0.i + q.q1 * b1.i + q.q2 * b1.r;
+  o.c[1].r = q.mm * a1.r + q.q1 * b0.r + q.q2 * b0.i + q.qm * b1.r;
+  o.c[1].i = q.mm * a1.i + q.q1 * b0.i - q.q2 * b0.r + q.qm * b1.i;
+  // (a Qs + mm b): a Qs = (a0 qm + a1 (-q1 - i q2), a0 (-q1 + i q2) + a1 qp)
+  o.c[2].r = q.mm * b0.r + q.qm * a0.r - q.q1 * a1.r + q.q2 * a1.i;
+  o.c[2].i = q.mm * b0.i + q.qm * a0.i - q.q1 * a1.i - q.q2 * a1.r;
+  o.c[3].r = q.mm * b1.r - q.q1 * a0.r - q.q2 * a0.i + q.qp * a1.r;
+  o.c[3].i = q.mm * b1.i - q.q1 * a0.i + q.q2 * a0.r + q.qp * a1.i;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Dot (the join after its propagator has been moved onto one side):
+// acc += Jbar . J = sum_k Jbar_k J_k.                                 32 FLOPs
+// ---------------------------------------------------------------------------
+template <class T> QEDX_HD void dot_acc(cx<T>& acc, const sp4<T>& B, const sp4<T>& J) {
+  T r = acc.r, i = acc.i;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r = r + B.c[k].r * J.c[k].r;
+    i = i + B.c[k].r * J.c[k].i;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r = r - B.c[k].i * J.c[k].i;
+    i = i + B.c[k].i * J.c[k].r;
+  }
+  acc.r = r;
+  acc.i = i;
+}
+template <class T> QEDX_HD cx<T> dot(const sp4<T>& B, const sp4<T>& J) {
+  cx<T> a{T(0), T(0)};
+  dot_acc(a, B, J);
+  return a;
+}
+
+// Error-free transformation of a sum (Knuth TwoSum): s + e == a + b exactly.
+template <class T> QEDX_HD void two_sum(T a, T b, T& s, T& e) {
+  s = a + b;
+  T bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+// Compensated accumulation of a complex value (FP32 path): 12 FLOPs.
+template <class T> QEDX_HD void comp_acc(cx<T>& s, cx<T>& c, const cx<T>& x) {
+  T e;
+  two_sum(s.r, x.r, s.r, e);
+  c.r = c.r + e;
+  two_sum(s.i, x.i, s.i, e);
+  c.i = c.i + e;
+}
+
+// ---------------------------------------------------------------------------
+// U: external states (base_state) from momenta, double precision.
+// u(p, s): psi_L = ((E+m) - p.sigma) chi / sqrt(2(E+m)),
+//          psi_R = ((E+m) + p.sigma) chi / sqrt(2(E+m)),  chi_0 = (1,0), chi_1 = (0,1).
+// ubar(p, s) = (conj psi_R, conj psi_L) as a row.
+// ---------------------------------------------------------------------------
+template <class T> QEDX_HD sp4<T> u_in(double E, double px, double py, double pz, int s, double m) {
+  double c = E + m;
+  double nrm = 1.0 / sqrt(2.0 * c);
+  sp4<T> o;
+  if (s == 0) {
+    o.c[0] = {T((c - pz) * nrm), T(0)};
+    o.c[1] = {T(-px * nrm), T(-py * nrm)};
+    o.c[2] = {T((c + pz) * nrm), T(0)};
+    o.c[3] = {T(px * nrm), T(py * nrm)};
+  } else {
+    o.c[0] = {T(-px * nrm), T(py * nrm)};
+    o.c[1] = {T((c + pz) * nrm), T(0)};
+    o.c[2] = {T(px * nrm), T(-py * nrm)};
+    o.c[3] = {T((c - pz) * nrm), T(0)};
+  }
+  return o;
+}
+template <class T> QEDX_HD sp4<T> ubar_out(double E, double px, double py, double pz, int s, double m) {
+  sp4<T> u = u_in<T>(E, px, py, pz, s, m);
+  sp4<T> o;
+  o.c[0] = {u.c[2].r, -u.c[2].i};
+  o.c[1] = {u.c[3].r, -u.c[3].i};
+  o.c[2] = {u.c[0].r, -u.c[0].i};
+  o.c[3] = {u.c[1].r, -u.c[1].i};
+  return o;
+}
+// Linear polarisation in the theta/phi basis of k-hat:
+// eps_x = (cos t cos f, cos t sin f, -sin t), eps_y = (-sin f, cos f, 0);
+// k_T = 0: f = 0 and cos t = sign(k_z).
+template <class T> QEDX_HD pol3<T> pol(double kx, double ky, double kz, int lam) {
+  double kt2 = kx * kx + ky * ky;
+  double kt = sqrt(kt2);
+  double kk = sqrt(kt2 + kz * kz);
+  double cf, sf, ct, st;
+  if (kt > 0.0) {
+    double ikt = 1.0 / kt;
+    double ikk = 1.0 / kk;
+    cf = kx * ikt;
+    sf = ky * ikt;
+    ct = kz * ikk;
+    st = kt * ikk;
+  } else {
+    cf = 1.0;
+    sf = 0.0;
+    ct = kz > 0.0 ? 1.0 : (kz < 0.0 ? -1.0 : 0.0);
+    st = 0.0;
+  }
+  pol3<T> e;
+  if (lam == 0) {
+    e.e1 = T(ct * cf);
+    e.e2 = T(ct * sf);
+    e.e3 = T(-st);
+  } else {
+    e.e1 = T(-sf);
+    e.e2 = T(cf);
+    e.e3 = T(0);
+  }
+  return e;
+}
+
+// Propagator coefficients from Q and D = Q^2 - m^2 (double precision).
+template <class T> QEDX_HD propq<T> prop_coeffs(double Q0, double Q1, double Q2, double Q3, double D, double m) {
+  double id = 1.0 / D;
+  propq<T> q;
+  q.qm = T((Q0 - Q3) * id);
+  q.qp = T((Q0 + Q3) * id);
+  q.q1 = T(Q1 * id);
+  q.q2 = T(Q2 * id);
+  q.mm = T(m * id);
+  return q;
+}
+
+// Propagator coefficients for Q = p + s K with p on shell and s = +-1:
+// Q^2 - m^2 = 2 s p.K + K^2, free of the cancellation in Q.Q - m^2.  28 FLOPs.
+template <class T>
+QEDX_HD propq<T> prop_from(double p0, double p1, double p2, double p3, double K0, double K1, double K2, double K3,
+                           double s, double m) {
+  double pK = p0 * K0 - p1 * K1 - p2 * K2 - p3 * K3;
+  double KK = K0 * K0 - K1 * K1 - K2 * K2 - K3 * K3;
+  double D = 2.0 * s * pK + KK;
+  return prop_coeffs<T>(p0 + s * K0, p1 + s * K1, p2 + s * K2, p3 + s * K3, D, m);
+}
+
+}  // namespace qx

@@ -1,0 +1,60 @@
+// qedx_emit.hpp -- HIP source generator for the reduced QED computation graph.
+#pragma once
+
+#include <cstdint>
+#include <string>
+
+#include "qedx_dag.hpp"
+
+namespace qedx {
+
+enum Prec : int { PREC_F64 = 0, PREC_F32C = 1 };
+enum HelMode : int { HEL_SUM = 0, HEL_PER_POINT = 1 };
+
+// How one kernel instance covers the helicity configurations of a point.
+//  - enum_mask: particle bits enumerated inside the graph (shared nodes);
+//  - lane_mask: bits taken from the lane index; 2^popcount lanes per point,
+//    summed with a wavefront butterfly at the end;
+//  - loop_mask: bits enumerated by a run-time loop around the graph body.
+// In HEL_PER_POINT mode every bit comes from the per-point input code.
+struct Variant {
+  int prec = PREC_F64;
+  int mode = HEL_SUM;
+  uint32_t enum_mask = 0, lane_mask = 0, loop_mask = 0;
+  int block = 256;      // threads per workgroup
+  int split = 1;        // photons attached on the e-_in side of every join
+  int join_side = 1;    // side whose current carries the join propagator
+  int order = 0;        // emission order strategy (0 = partition-grouped)
+  int min_waves = 0;    // __launch_bounds__ second argument (0 = none)
+};
+
+struct EmitStats {
+  double flops_per_point = 0;   // algorithmic FLOPs per phase-space point
+  int64_t n_V = 0, n_S1 = 0, n_dot = 0, n_prop = 0, n_U = 0;
+  int64_t lines = 0;
+};
+
+// Canonical text of a variant (part of the code-object cache key).
+std::string variant_tag(const Variant& v, int n_out, int n_in);
+
+// Build the graph for (process, variant): generate, reduce, expand joins,
+// reduce again.  Timings (ms) are written to t_build / t_reduce if non-null.
+Dag graph_for(const Process& proc, const Variant& v, double* t_build, double* t_reduce);
+
+// Emit a self-contained HIP translation unit with the device header inlined
+// and one kernel
+//   extern "C" __global__ void <kname>(const double* mom, const unsigned* hel,
+//                                      long long N, double* out)
+// mom: [4*npart][N] SoA (row = 4*particle + mu), out: [N].
+std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* st);
+
+// Device function text of one process body (used by the mixed batch module):
+//   __device__ double <fname>(const double* mom, long long N, long long pt,
+//                             unsigned hrt)
+// returning the per-lane partial sum of |A|^2.
+std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* st);
+
+// The device header text (inlined into every generated unit).
+const std::string& device_header_text();
+
+}  // namespace qedx

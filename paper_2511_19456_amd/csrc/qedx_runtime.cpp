@@ -1,0 +1,593 @@
+// qedx_runtime.cpp -- the C ABI of include/qedx.h: process creation (graph
+// build, node reduction, code generation, code-object cache, module load),
+// launches, and the host-side graph tools.
+#include <dlfcn.h>
+#include <fcntl.h>
+#include <signal.h>
+#include <hip/hip_runtime_api.h>
+#include <spawn.h>
+#include <sys/stat.h>
+#include <sys/wait.h>
+#include <unistd.h>
+
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/qedx.h"
+#include "qedx_dag.hpp"
+#include "qedx_emit.hpp"
+#include "qedx_kernels.hpp"
+
+extern char** environ;
+
+using namespace qedx;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static qed_status fail(qed_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+extern "C" const char* qed_last_error(void) { return g_err.c_str(); }
+
+#define HIPCHK(expr)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return fail(QED_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// cache directory and compiler
+// ---------------------------------------------------------------------------
+static std::string lib_dir() {
+  Dl_info info;
+  if (dladdr((void*)&qed_last_error, &info) && info.dli_fname) {
+    std::string p(info.dli_fname);
+    auto s = p.rfind('/');
+    if (s != std::string::npos) return p.substr(0, s);
+  }
+  return ".";
+}
+
+static std::string& cache_dir_str() {
+  static std::string dir = [] {
+    const char* e = getenv("QEDX_CACHE_DIR");
+    std::string d = e && *e ? std::string(e) : lib_dir() + "/kcache";
+    mkdir(d.c_str(), 0755);
+    return d;
+  }();
+  return dir;
+}
+
+extern "C" const char* qed_cache_dir(void) { return cache_dir_str().c_str(); }
+
+static uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* p = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
+}
+
+static std::string hex64(uint64_t v) {
+  char b[20];
+  snprintf(b, sizeof b, "%016llx", (unsigned long long)v);
+  return b;
+}
+
+static const char* kArch = "gfx950";
+
+static std::vector<std::string> compile_flags() {
+  std::vector<std::string> f = {"--offload-arch=gfx950",
+                                "-O3",
+                                "--genco",
+                                "-std=c++17",
+                                "-ffp-contract=fast",
+                                "-Xclang",
+                                "-target-feature",
+                                "-Xclang",
+                                "-packed-fp32-ops",
+                                "-Rpass-analysis=kernel-resource-usage"};
+  if (const char* x = getenv("QEDX_EXTRA_FLAGS")) {
+    std::istringstream is(x);
+    std::string t;
+    while (is >> t) f.push_back(t);
+  }
+  return f;
+}
+
+static std::string hipcc_path() {
+  const char* r = getenv("ROCM_PATH");
+  std::string base = r && *r ? r : "/opt/rocm";
+  return base + "/bin/hipcc";
+}
+
+static bool read_file(const std::string& path, std::string& out) {
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return false;
+  std::ostringstream ss;
+  ss << f.rdbuf();
+  out = ss.str();
+  return true;
+}
+
+static bool write_file(const std::string& path, const std::string& data) {
+  std::string tmp = path + ".tmp" + std::to_string(getpid()) + "_" +
+                    std::to_string(std::hash<std::thread::id>()(std::this_thread::get_id()));
+  {
+    std::ofstream f(tmp, std::ios::binary);
+    if (!f) return false;
+    f.write(data.data(), (std::streamsize)data.size());
+    if (!f) return false;
+  }
+  return rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+// Run hipcc as a child process (never replaces this process).
+static int run_hipcc(const std::string& src, const std::string& out, const std::string& log, double timeout_s) {
+  std::vector<std::string> args = {hipcc_path()};
+  for (auto& f : compile_flags()) args.push_back(f);
+  args.push_back(src);
+  args.push_back("-o");
+  args.push_back(out);
+  std::vector<char*> argv;
+  for (auto& a : args) argv.push_back((char*)a.c_str());
+  argv.push_back(nullptr);
+  posix_spawn_file_actions_t fa;
+  posix_spawn_file_actions_init(&fa);
+  posix_spawn_file_actions_addopen(&fa, 1, log.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0644);
+  posix_spawn_file_actions_adddup2(&fa, 1, 2);
+  pid_t pid;
+  int rc = posix_spawn(&pid, argv[0], &fa, nullptr, argv.data(), environ);
+  posix_spawn_file_actions_destroy(&fa);
+  if (rc != 0) return -1000 - rc;
+  auto t0 = std::chrono::steady_clock::now();
+  int status = 0;
+  while (true) {
+    pid_t w = waitpid(pid, &status, WNOHANG);
+    if (w == pid) break;
+    if (w < 0) return -2000;
+    double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (el > timeout_s) {
+      kill(pid, SIGKILL);
+      waitpid(pid, &status, 0);
+      return -3000;
+    }
+    std::this_thread::sleep_for(std::chrono::milliseconds(20));
+  }
+  return WIFEXITED(status) ? WEXITSTATUS(status) : -4000;
+}
+
+struct KernelMeta {
+  int vgpr = -1, agpr = -1, sgpr = -1, scratch = -1, lds = -1, occupancy = -1;
+};
+
+static KernelMeta parse_meta(const std::string& log) {
+  KernelMeta m;
+  auto grab = [&](const char* key, int& v) {
+    auto p = log.find(key);
+    if (p != std::string::npos) v = atoi(log.c_str() + p + strlen(key));
+  };
+  grab(" VGPRs: ", m.vgpr);
+  grab(" AGPRs: ", m.agpr);
+  grab(" SGPRs: ", m.sgpr);
+  grab("ScratchSize [bytes/lane]: ", m.scratch);
+  grab("LDS Size [bytes/block]: ", m.lds);
+  grab("Occupancy [waves/SIMD]: ", m.occupancy);
+  return m;
+}
+
+// Compile (or find) the code object for a generated source.  Thread-safe.
+// Returns the code object bytes; *hit = cache hit; *ms = compile time.
+static std::mutex g_cache_mu;
+
+static qed_status get_code_object(const std::string& tag, const std::string& src, std::string& co,
+                                  KernelMeta& meta, bool& hit, double& ms) {
+  std::string key_material = src;
+  for (auto& f : compile_flags()) key_material += "\n" + f;
+  key_material += std::string("\n") + kArch;
+  std::string h = hex64(fnv1a(key_material.data(), key_material.size()));
+  std::string base = cache_dir_str() + "/" + tag + "-" + h;
+  std::string path = base + ".hsaco", sum = base + ".sum", log = base + ".log";
+  hit = false;
+  ms = 0;
+  {
+    std::string s, chk;
+    if (read_file(path, co) && read_file(sum, chk) && chk == hex64(fnv1a(co.data(), co.size()))) {
+      std::string lg;
+      read_file(log, lg);
+      meta = parse_meta(lg);
+      hit = true;
+      return QED_OK;
+    }
+  }
+  if (getenv("QEDX_NO_COMPILE"))
+    return fail(QED_ERR_COMPILE, "code object " + path + " missing or corrupt and QEDX_NO_COMPILE is set");
+  std::string srcp = base + ".hip";
+  if (!write_file(srcp, src)) return fail(QED_ERR_COMPILE, "cannot write " + srcp);
+  std::string tmpo = base + ".o.tmp" + std::to_string(getpid()) + "_" +
+                     std::to_string(std::hash<std::thread::id>()(std::this_thread::get_id()));
+  std::string tmpl = log + ".tmp" + std::to_string(getpid()) + "_" +
+                     std::to_string(std::hash<std::thread::id>()(std::this_thread::get_id()));
+  double tmo = 3600.0;
+  if (const char* t = getenv("QEDX_COMPILE_TIMEOUT")) tmo = atof(t);
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = run_hipcc(srcp, tmpo, tmpl, tmo);
+  ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  std::string lg;
+  read_file(tmpl, lg);
+  if (rc != 0 || !read_file(tmpo, co) || co.empty()) {
+    unlink(tmpo.c_str());
+    unlink(tmpl.c_str());
+    return fail(QED_ERR_COMPILE, "hipcc failed (rc " + std::to_string(rc) + ") for " + srcp + ":\n" +
+                                     lg.substr(0, 4000));
+  }
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  rename(tmpl.c_str(), log.c_str());
+  rename(tmpo.c_str(), path.c_str());
+  write_file(sum, hex64(fnv1a(co.data(), co.size())));
+  meta = parse_meta(lg);
+  return QED_OK;
+}
+
+// ---------------------------------------------------------------------------
+// processes
+// ---------------------------------------------------------------------------
+struct qed_process {
+  int n = 0;
+  qed_hel_mode mode = QED_HEL_SUM;
+  qed_precision prec = QED_FP64;
+  Variant var;
+  Process proc;
+  qed_info info{};
+  int lanes = 1;
+  hipModule_t mod = nullptr;
+  hipFunction_t f_eval = nullptr;
+  hipModule_t mod_aux = nullptr;  // RAMBO and gradient kernels
+  hipFunction_t f_rambo = nullptr;
+  hipFunction_t f_grad = nullptr;
+  int grad_block = 64;
+  std::string eval_src;
+};
+
+static void default_variant(int n, qed_hel_mode mode, qed_precision prec, Variant& v) {
+  v = Variant();
+  v.prec = prec == QED_FP64 ? PREC_F64 : PREC_F32C;
+  v.mode = mode == QED_HEL_SUM ? HEL_SUM : HEL_PER_POINT;
+  int P = n + 1;
+  v.split = P / 2;
+  v.block = 256;
+  v.join_side = 1;
+  if (mode == QED_HEL_SUM) {
+    uint32_t all = (1u << (n + 3)) - 1;
+    // electron spins over lanes; photon polarisations shared in the graph
+    // for small n, partly looped for larger n
+    v.lane_mask = (1u << 0) | (1u << 2);
+    uint32_t photons = all & ~v.lane_mask;
+    if (n <= 3) {
+      v.enum_mask = photons;
+    } else {
+      // keep 2^3 configurations inside the graph, loop over the rest
+      uint32_t e = 0;
+      int k = 0;
+      for (int b = 0; b < n + 3 && k < 3; ++b)
+        if ((photons >> b) & 1) {
+          e |= 1u << b;
+          ++k;
+        }
+      v.enum_mask = e;
+      v.loop_mask = photons & ~e;
+    }
+  }
+}
+
+static qed_status make_variant(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* qv, Variant& v) {
+  default_variant(n, mode, prec, v);
+  if (qv && !qv->use_defaults) {
+    if (qv->block) v.block = qv->block;
+    if (qv->split) v.split = qv->split;
+    v.min_waves = qv->min_waves;
+    if (qv->order) v.order = qv->order;
+    if (mode == QED_HEL_SUM) {
+      uint32_t all = (1u << (n + 3)) - 1;
+      v.lane_mask = qv->lane_bits & all;
+      v.loop_mask = qv->loop_bits & all & ~v.lane_mask;
+      v.enum_mask = all & ~v.lane_mask & ~v.loop_mask;
+    } else if (qv->lane_bits || qv->loop_bits) {
+      return fail(QED_ERR_INVALID_ARG, "lane_bits/loop_bits apply to SUM mode only");
+    }
+  }
+  if (v.block % 64 || v.block < 64 || v.block > 1024) return fail(QED_ERR_INVALID_ARG, "block must be 64..1024, multiple of 64");
+  if (v.split < 1 || v.split > n) return fail(QED_ERR_INVALID_ARG, "split must be in 1..n");
+  if (__builtin_popcount(v.lane_mask) > 6) return fail(QED_ERR_INVALID_ARG, "at most 6 lane bits");
+  return QED_OK;
+}
+
+static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* qv, Variant& v,
+                               Process& proc, std::string& src, qed_info& info) {
+  if (n < 1 || n > 6) return fail(QED_ERR_UNSUPPORTED, "n must be in 1..6");
+  if (mode != QED_HEL_SUM && mode != QED_HEL_PER_POINT) return fail(QED_ERR_INVALID_ARG, "bad helicity mode");
+  if (prec != QED_FP64 && prec != QED_FP32C) return fail(QED_ERR_INVALID_ARG, "bad precision");
+  qed_status s = make_variant(n, mode, prec, qv, v);
+  if (s) return s;
+  proc = Process::make(n, 1);
+  try {
+    double tb = 0, tr = 0;
+    Dag un = build_unreduced(proc, v.enum_mask, v.split);
+    info.nodes_unreduced = (int64_t)un.nodes.size();
+    un = Dag();
+    Dag d = graph_for(proc, v, &tb, &tr);
+    info.create_ms_build = tb;
+    info.create_ms_reduce = tr;
+    info.nodes_reduced = (int64_t)d.nodes.size();
+    auto t0 = std::chrono::steady_clock::now();
+    EmitStats st;
+    src = emit_eval_kernel(d, v, "qedx_eval", &st);
+    info.create_ms_emit = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    info.n_V = st.n_V;
+    info.n_S1 = st.n_S1;
+    info.n_dot = st.n_dot;
+    info.n_prop = st.n_prop;
+    info.flops_per_point = st.flops_per_point;
+  } catch (const std::exception& e) {
+    return fail(QED_ERR_INVALID_ARG, std::string("graph/emit: ") + e.what());
+  }
+  info.n = n;
+  info.mode = mode;
+  info.precision = prec;
+  info.lanes_per_point = 1 << __builtin_popcount(v.lane_mask);
+  info.block = v.block;
+  std::string tag = variant_tag(v, n, 1);
+  snprintf(info.kernel_tag, sizeof info.kernel_tag, "%s", tag.c_str());
+  return QED_OK;
+}
+
+extern "C" qed_status qed_emit_source(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
+                                      char* buf, int64_t buflen, int64_t* len) {
+  Variant v;
+  Process proc;
+  std::string src;
+  qed_info info{};
+  qed_status s = build_source(n, mode, prec, variant, v, proc, src, info);
+  if (s) return s;
+  if (len) *len = (int64_t)src.size();
+  if (buf && buflen > 0) {
+    size_t m = std::min<size_t>((size_t)buflen - 1, src.size());
+    memcpy(buf, src.data(), m);
+    buf[m] = 0;
+  }
+  return QED_OK;
+}
+
+// Emit + compile into the cache without touching the GPU (used to prebuild).
+extern "C" qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
+                                   int with_aux, double* compile_ms) {
+  Variant v;
+  Process proc;
+  std::string src;
+  qed_info info{};
+  qed_status s = build_source(n, mode, prec, variant, v, proc, src, info);
+  if (s) return s;
+  std::string co;
+  KernelMeta meta;
+  bool hit;
+  double ms = 0, ms2 = 0;
+  s = get_code_object(info.kernel_tag, src, co, meta, hit, ms);
+  if (s) return s;
+  if (with_aux) {
+    std::string asrc = emit_aux_module(proc, v, n);
+    std::string atag = std::string("aux_") + info.kernel_tag;
+    s = get_code_object(atag, asrc, co, meta, hit, ms2);
+    if (s) return s;
+  }
+  if (compile_ms) *compile_ms = ms + ms2;
+  return QED_OK;
+}
+
+extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
+                                         qed_process** out) {
+  if (!out) return fail(QED_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  auto p = std::make_unique<qed_process>();
+  qed_status s = build_source(n, mode, prec, variant, p->var, p->proc, p->eval_src, p->info);
+  if (s) return s;
+  p->n = n;
+  p->mode = mode;
+  p->prec = prec;
+  p->lanes = p->info.lanes_per_point;
+  std::string co;
+  KernelMeta meta;
+  bool hit = false;
+  double ms = 0;
+  s = get_code_object(p->info.kernel_tag, p->eval_src, co, meta, hit, ms);
+  if (s) return s;
+  p->info.create_ms_compile = ms;
+  p->info.cache_hit = hit ? 1 : 0;
+  p->info.vgpr = meta.vgpr;
+  p->info.agpr = meta.agpr;
+  p->info.sgpr = meta.sgpr;
+  p->info.scratch_bytes = meta.scratch;
+  p->info.lds_bytes = meta.lds;
+  auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(hipModuleLoadData(&p->mod, co.data()));
+  HIPCHK(hipModuleGetFunction(&p->f_eval, p->mod, "qedx_eval"));
+  // auxiliary module: RAMBO (all processes) and the gradient kernel
+  std::string asrc = emit_aux_module(p->proc, p->var, n);
+  std::string aco;
+  KernelMeta am;
+  bool ahit;
+  double ams;
+  s = get_code_object(std::string("aux_") + p->info.kernel_tag, asrc, aco, am, ahit, ams);
+  if (s) return s;
+  p->info.create_ms_compile += ams;
+  HIPCHK(hipModuleLoadData(&p->mod_aux, aco.data()));
+  HIPCHK(hipModuleGetFunction(&p->f_rambo, p->mod_aux, "qedx_rambo"));
+  if (hipModuleGetFunction(&p->f_grad, p->mod_aux, "qedx_grad") != hipSuccess) p->f_grad = nullptr;
+  (void)hipGetLastError();
+  p->info.create_ms_load = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = p.release();
+  return QED_OK;
+}
+
+extern "C" qed_status qed_process_destroy(qed_process* p) {
+  if (!p) return QED_OK;
+  if (p->mod) (void)hipModuleUnload(p->mod);
+  if (p->mod_aux) (void)hipModuleUnload(p->mod_aux);
+  delete p;
+  return QED_OK;
+}
+
+extern "C" qed_status qed_process_info(const qed_process* p, qed_info* out) {
+  if (!p || !out) return fail(QED_ERR_INVALID_ARG, "NULL argument");
+  *out = p->info;
+  return QED_OK;
+}
+
+static qed_status launch(hipFunction_t f, int64_t threads, int block, void* stream, void** args) {
+  int64_t grid = (threads + block - 1) / block;
+  if (grid > 0x7fffffff) return fail(QED_ERR_INVALID_ARG, "N too large for one launch");
+  HIPCHK(hipModuleLaunchKernel(f, (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0, (hipStream_t)stream, args,
+                               nullptr));
+  return QED_OK;
+}
+
+extern "C" qed_status qed_eval(const qed_process* p, const double* momenta, const uint32_t* hel, int64_t N,
+                               double* out, void* stream) {
+  if (!p) return fail(QED_ERR_INVALID_ARG, "process is NULL");
+  if (N < 0) return fail(QED_ERR_INVALID_ARG, "N < 0");
+  if (p->mode == QED_HEL_SUM && hel) return fail(QED_ERR_INVALID_ARG, "hel must be NULL in SUM mode");
+  if (N == 0) return QED_OK;
+  if (!momenta || !out) return fail(QED_ERR_INVALID_ARG, "NULL buffer");
+  if (p->mode == QED_HEL_PER_POINT && !hel) return fail(QED_ERR_INVALID_ARG, "hel required in PER_POINT mode");
+  if (N > (int64_t)1 << 40) return fail(QED_ERR_INVALID_ARG, "N too large");
+  long long n = (long long)N;
+  void* args[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out};
+  return launch(p->f_eval, N * (int64_t)p->lanes, p->var.block, stream, args);
+}
+
+extern "C" qed_status qed_rambo(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N,
+                                double* momenta_out, void* stream) {
+  if (!p) return fail(QED_ERR_INVALID_ARG, "process is NULL");
+  if (N < 0) return fail(QED_ERR_INVALID_ARG, "N < 0");
+  if (!(sqrt_s > 1.0) || !std::isfinite(sqrt_s)) return fail(QED_ERR_INVALID_ARG, "sqrt_s must exceed m = 1");
+  if (N == 0) return QED_OK;
+  if (!uniforms || !momenta_out) return fail(QED_ERR_INVALID_ARG, "NULL buffer");
+  long long n = (long long)N;
+  void* args[] = {(void*)&uniforms, (void*)&sqrt_s, (void*)&n, (void*)&momenta_out};
+  return launch(p->f_rambo, N, 256, stream, args);
+}
+
+extern "C" qed_status qed_eval_grad(const qed_process* p, const double* uniforms, double sqrt_s,
+                                    const uint32_t* hel, int64_t N, double* out_logm2, double* out_grad,
+                                    void* stream) {
+  if (!p) return fail(QED_ERR_INVALID_ARG, "process is NULL");
+  if (p->mode != QED_HEL_SUM || p->prec != QED_FP64)
+    return fail(QED_ERR_UNSUPPORTED, "gradient is built for SUM-mode FP64 processes");
+  if (hel) return fail(QED_ERR_INVALID_ARG, "hel must be NULL");
+  if (N < 0) return fail(QED_ERR_INVALID_ARG, "N < 0");
+  if (!(sqrt_s > 1.0) || !std::isfinite(sqrt_s)) return fail(QED_ERR_INVALID_ARG, "sqrt_s must exceed m = 1");
+  if (!p->f_grad) return fail(QED_ERR_UNSUPPORTED, "no gradient kernel for this process variant");
+  if (N == 0) return QED_OK;
+  if (!uniforms || !out_logm2 || !out_grad) return fail(QED_ERR_INVALID_ARG, "NULL buffer");
+  long long n = (long long)N;
+  void* args[] = {(void*)&uniforms, (void*)&sqrt_s, (void*)&n, (void*)&out_logm2, (void*)&out_grad};
+  return launch(p->f_grad, N * (int64_t)p->lanes, p->grad_block, stream, args);
+}
+
+// ---------------------------------------------------------------------------
+// host graph tools
+// ---------------------------------------------------------------------------
+static Dag tool_graph(int n, int n_in, uint32_t enum_mask, int split, int reduced) {
+  Process pr = Process::make(n, n_in);
+  Dag d = build_unreduced(pr, enum_mask, split);
+  if (reduced) {
+    d = reduce_fixpoint(d);
+    d = compact(reduce_fixpoint(expand_joins(d, 1)));
+  }
+  return d;
+}
+
+static qed_status check_tool_args(int n, int n_in, uint32_t enum_mask, int split) {
+  if (n < 1 || n_in < 1 || n + n_in > 9) return fail(QED_ERR_INVALID_ARG, "need n >= 1, n_in >= 1, n + n_in <= 9");
+  if (split < 1 || split >= n + n_in) return fail(QED_ERR_INVALID_ARG, "split must be in 1..P-1");
+  if (enum_mask >> (n + n_in + 2)) return fail(QED_ERR_INVALID_ARG, "enum_mask has bits beyond the particles");
+  return QED_OK;
+}
+
+extern "C" qed_status qed_graph_counts(int n, int n_in, uint32_t enum_mask, int split, int reduced,
+                                       int64_t* counts) {
+  if (!counts) return fail(QED_ERR_INVALID_ARG, "counts is NULL");
+  qed_status s = check_tool_args(n, n_in, enum_mask, split);
+  if (s) return s;
+  try {
+    Dag d = tool_graph(n, n_in, enum_mask, split, reduced);
+    Counts c = count(d);
+    int64_t v[10] = {c.total, c.data, c.compute, c.U, c.V, c.S1, c.S2, c.Dot, c.Sum, c.HelSum};
+    memcpy(counts, v, sizeof v);
+  } catch (const std::bad_alloc&) {
+    return fail(QED_ERR_OOM, "graph too large");
+  }
+  return QED_OK;
+}
+
+extern "C" qed_status qed_graph_interpret(int n, int n_in, uint32_t enum_mask, int split, int reduced,
+                                          const double* mom, const uint32_t* hel, int64_t N, double* out) {
+  qed_status s = check_tool_args(n, n_in, enum_mask, split);
+  if (s) return s;
+  if (N < 0 || (N > 0 && (!mom || !out))) return fail(QED_ERR_INVALID_ARG, "bad buffers");
+  Dag d = tool_graph(n, n_in, enum_mask, split, reduced);
+  int np = n + n_in + 2;
+  for (int64_t i = 0; i < N; ++i) out[i] = interpret(d, mom + 4 * np * i, hel ? hel[i] : 0u);
+  return QED_OK;
+}
+
+extern "C" qed_status qed_graph_reduction_check(int n, int n_in, uint32_t enum_mask, int split, uint64_t seed,
+                                                char* canon_a, char* canon_b, int64_t buflen, int64_t* steps) {
+  qed_status s = check_tool_args(n, n_in, enum_mask, split);
+  if (s) return s;
+  Process pr = Process::make(n, n_in);
+  Dag u = build_unreduced(pr, enum_mask, split);
+  Dag a = compact(reduce_fixpoint(u));
+  Dag b = u;
+  int64_t k = reduce_random_order(b, seed);
+  if (steps) *steps = k;
+  std::string ca = canonical(a), cb = canonical(b);
+  auto put = [&](char* dst, const std::string& src) {
+    if (!dst || buflen <= 0) return;
+    size_t m = std::min<size_t>((size_t)buflen - 1, src.size());
+    memcpy(dst, src.data(), m);
+    dst[m] = 0;
+  };
+  put(canon_a, ca);
+  put(canon_b, cb);
+  return QED_OK;
+}
+
+extern "C" qed_status qed_graph_metrics(int n, int n_in, uint32_t enum_mask, int split, int reduced, int fp32,
+                                        double* c_dag, double* d_dag) {
+  qed_status s = check_tool_args(n, n_in, enum_mask, split);
+  if (s) return s;
+  Dag d = tool_graph(n, n_in, enum_mask, split, reduced);
+  if (c_dag) *c_dag = compute_effort(d, fp32 != 0);
+  if (d_dag) *d_dag = data_transfer(d, fp32 != 0);
+  return QED_OK;
+}
+
+// ---------------------------------------------------------------------------
+// mixed-process batches (persistent kernel) -- see qedx_batch.cpp
+// ---------------------------------------------------------------------------

@@ -80,8 +80,9 @@ class QedVariant(ctypes.Structure):
 
 # (n, mode, precision) built ahead of time: SUM 0 / PER_POINT 1; FP64 0 / FP32C 1
 DEFAULT_KERNELS = [
-    (1, 0, 0), (2, 0, 0), (3, 0, 0),
-    (1, 1, 0), (2, 1, 0), (3, 1, 0), (5, 1, 0),
+    (1, 0, 0), (2, 0, 0), (3, 0, 0), (4, 0, 0),
+    (1, 1, 0), (2, 1, 0), (3, 1, 0), (4, 1, 0), (5, 1, 0),
+    (3, 0, 1), (5, 1, 1),
 ]
 
 

@@ -119,6 +119,8 @@ struct Emitter {
     return "(int)((hc >> " + std::to_string(u.particle) + ") & 1u)";
   }
 
+  bool local() const { return (v.order & 4) != 0; }
+
   // scheduling fence: keeps LLVM's machine scheduler from moving work across
   void fence(int level) {
     if (v.order & level) os << ind << "__builtin_amdgcn_sched_barrier(0);\n";
@@ -252,6 +254,22 @@ struct Emitter {
       const std::set<int>& stream = holdB ? Js : Bs;
       fence(1);
       os << ind << "// photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << " on the e-_in | e-_out side\n";
+      std::string outer = ind;
+      if (local()) {
+        // Partition-local block: momenta reloaded through an index the
+        // compiler cannot see through, so nothing computed here is merged
+        // with (and kept live from) another partition's block.
+        // A uniform branch on an opaque flag puts the block in its own basic
+        // block, so instruction selection schedules it on its own.
+        os << ind << "{\n" << ind << "  int live = 1;\n" << ind << "  asm volatile(\"\" : \"+s\"(live));\n"
+           << ind << "  if (live) {\n";
+        ind += "    ";
+        os << ind << "long long pq = ptc;\n" << ind << "asm volatile(\"\" : \"+v\"(pq));\n";
+        load_momenta("mom", "N", "pq");
+        std::fill(done.begin(), done.end(), 0);
+        kdone.clear();
+        qdone.clear();
+      }
       for (int h : hold) emit(h);
       for (int s : stream) {
         emit(s);
@@ -260,6 +278,10 @@ struct Emitter {
           int sp = producer(holdB ? ops.first : ops.second);
           if (sp == s) emit_dot(k);
         }
+      }
+      if (local()) {
+        ind = outer;
+        os << ind << "  }\n" << ind << "}\n";
       }
     }
     // |A|^2, summed over the enumerated configurations (HelSum) or single
@@ -345,7 +367,7 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   os << "  const long long pt = gid >> " << LB << ";\n";
   os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
   os << "  const long long ptc = pt < N ? pt : N - 1;\n";
-  e.load_momenta("mom", "N", "ptc");
+  if (!e.local()) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
   std::string hrt = v.mode == HEL_PER_POINT ? "hel[ptc]" : Emitter::deposit("sub", v.lane_mask);
   e.lane_work(hrt);
@@ -365,7 +387,7 @@ std::string emit_body_function(const Dag& d, const Variant& v, const std::string
   std::ostringstream& os = e.os;
   os << "static __device__ double " << fname
      << "(const double* __restrict__ mom, long long N, long long ptc, unsigned hrt_in)\n{\n";
-  e.load_momenta("mom", "N", "ptc");
+  if (!e.local()) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
   e.lane_work("hrt_in");
   os << "  return acc;\n}\n";

@@ -273,6 +273,10 @@ static void default_variant(int n, qed_hel_mode mode, qed_precision prec, Varian
   v.split = P / 2;
   v.block = 256;
   v.join_side = 1;
+  // n <= 3: one shared graph per lane (few partitions, registers suffice);
+  // n >= 4: one basic block per photon partition with its currents
+  // recomputed there, which bounds the live set (measured faster).
+  v.order = n >= 4 ? 4 : 0;
   if (mode == QED_HEL_SUM) {
     uint32_t all = (1u << (n + 3)) - 1;
     // electron spins over lanes; photon polarisations shared in the graph

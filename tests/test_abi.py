@@ -1,0 +1,98 @@
+"""The C ABI: the library loads without a GPU and exports every function
+declared in include/qedx.h; the generated kernel source is self-contained."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2511_19456_amd import _lib
+from paper_2511_19456_amd import qedx as Q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(qed_\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    # and the binding declares every one of them
+    assert set(names) <= set(_lib.SIGNATURES)
+
+
+def test_emitted_source_is_self_contained():
+    src = Q.emit_source(2, "sum", "fp64")
+    assert 'extern "C" __global__' in src and "qedx_eval" in src
+    assert "#include \"" not in src  # device header is inlined
+    src = Q.emit_source(5, "per_point", "fp32c")
+    assert "comp_acc" in src and "qx::dot<float>" in src
+
+
+def test_status_codes_for_bad_processes():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.qed_process_create(0, 0, 0, None, ctypes.byref(h)) == _lib.QED_ERR_UNSUPPORTED
+    assert L.qed_process_create(7, 0, 0, None, ctypes.byref(h)) == _lib.QED_ERR_UNSUPPORTED
+    assert L.qed_process_create(3, 5, 0, None, ctypes.byref(h)) == _lib.QED_ERR_INVALID_ARG
+    assert L.qed_process_create(3, 0, 9, None, ctypes.byref(h)) == _lib.QED_ERR_INVALID_ARG
+    assert L.qed_process_create(3, 0, 0, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert b"n must be" in L.qed_last_error() or len(L.qed_last_error()) > 0
+    v = _lib.QedVariant(0, 0, 100, 0, 0, 0, 0)
+    assert L.qed_process_create(3, 0, 0, ctypes.byref(v), ctypes.byref(h)) == _lib.QED_ERR_INVALID_ARG
+    v = _lib.QedVariant(1, 0, 0, 0, 0, 0, 0)
+    assert L.qed_process_create(3, 1, 0, ctypes.byref(v), ctypes.byref(h)) == _lib.QED_ERR_INVALID_ARG
+
+
+def test_null_process_and_negative_sizes():
+    L = _lib.lib()
+    assert L.qed_eval(None, None, None, 0, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert L.qed_rambo(None, None, 10.0, 0, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert L.qed_eval_grad(None, None, 10.0, None, 0, None, None, None) == _lib.QED_ERR_INVALID_ARG
+
+
+def test_compile_failure_is_reported(tmp_path, monkeypatch):
+    """A broken compiler flag must surface as QED_ERR_COMPILE with hipcc's message."""
+    import subprocess
+    import sys
+    code = (
+        "import ctypes, sys; sys.path.insert(0, %r)\n"
+        "from paper_2511_19456_amd import _lib\n"
+        "L = _lib.lib(); ms = ctypes.c_double()\n"
+        "rc = L.qed_prebuild(1, 1, 0, None, 0, ctypes.byref(ms))\n"
+        "print(rc); print(L.qed_last_error().decode()[:200])\n" % ROOT)
+    env = dict(os.environ, QEDX_CACHE_DIR=str(tmp_path), QEDX_EXTRA_FLAGS="--this-flag-does-not-exist")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    lines = r.stdout.strip().splitlines()
+    assert lines[0] == str(_lib.QED_ERR_COMPILE), r.stdout + r.stderr
+    assert "hipcc failed" in r.stdout
+
+
+def test_corrupt_cache_entry_is_rebuilt(tmp_path):
+    """A code object whose checksum does not match is recompiled, not loaded."""
+    import subprocess
+    import sys
+    code = (
+        "import ctypes, sys, glob; sys.path.insert(0, %r)\n"
+        "from paper_2511_19456_amd import _lib\n"
+        "L = _lib.lib(); ms = ctypes.c_double()\n"
+        "assert L.qed_prebuild(1, 1, 0, None, 0, ctypes.byref(ms)) == 0\n"
+        "f = [x for x in glob.glob(%r + '/*.hsaco') if 'aux' not in x][0]\n"
+        "open(f, 'r+b').write(b'garbage!')\n"
+        "ms2 = ctypes.c_double()\n"
+        "assert L.qed_prebuild(1, 1, 0, None, 0, ctypes.byref(ms2)) == 0\n"
+        "print(ms.value > 0, ms2.value > 0)\n" % (ROOT, str(tmp_path)))
+    env = dict(os.environ, QEDX_CACHE_DIR=str(tmp_path))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    assert r.stdout.strip() == "True True", r.stdout + r.stderr

@@ -1,0 +1,135 @@
+"""Host-side tests of the CDAG generator, node reduction and cost model.
+
+Pins: Table I node counts (golden file, the paper's printed values), the App. D
+wiring of the one-photon graph, computational equivalence of the reduced graph
+(App. B-C) against the unreduced one and against the CPU oracle, and the
+uniqueness of the reduction fixpoint (Sec. III-D).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import qed_oracle as O
+from paper_2511_19456_amd import inputs
+from paper_2511_19456_amd import qedx as Q
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table1():
+    rows = {}
+    for line in open(os.path.join(GOLD, "table1_node_counts.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        n, c = line.split()
+        rows[int(n)] = int(c)
+    return rows
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7])
+def test_table1_node_counts_paper_orientation(n):
+    """e- gamma^n -> e- gamma: n incoming photons, one outgoing (the paper's process)."""
+    c = Q.graph_counts(1, n_in=n, split=(n + 1) // 2, reduced=False)
+    assert c["total"] == _table1()[n]
+    P = n + 1
+    assert c["V"] == P * math.factorial(P)
+    assert c["S1"] == (P - 2) * math.factorial(P)
+    assert c["S2"] == math.factorial(P)
+    assert c["U"] == n + 3 and c["Sum"] == 1
+    assert c["data"] == c["compute"] + (n + 3)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_node_counts_workload_orientation(n):
+    """e- gamma -> e- n gamma has the same graph size (crossing)."""
+    c = Q.graph_counts(n, n_in=1, reduced=False)
+    assert c["total"] == _table1()[n]
+
+
+def test_appD_one_photon_graph():
+    want = {}
+    for line in open(os.path.join(GOLD, "appD_n1_graph.txt")):
+        if line.startswith("count"):
+            _, k, v = line.split()
+            want[k] = int(v)
+    c = Q.graph_counts(1, reduced=False, split=1)
+    for k in ("U", "V", "S2", "Sum", "data", "total"):
+        assert c[k] == want[k]
+    # nothing is shared in the one-photon graph: reduction leaves it as is
+    r = Q.graph_counts(1, reduced=True, split=1)
+    assert r["V"] == 4 and r["Dot"] == 2
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_reduced_counts_are_prefix_tries(n):
+    """After reduction the vertices of each side form the trie of ordered photon
+    prefixes: sum over levels i of P!/(P-i)!."""
+    P = n + 1
+    j = P // 2
+    c = Q.graph_counts(n, reduced=True, split=j)
+    levels = lambda m: sum(math.factorial(P) // math.factorial(P - i) for i in range(1, m + 1))
+    assert c["V"] == levels(j) + levels(P - j)
+    assert c["Dot"] == math.factorial(P)
+    # chain propagators on both sides plus one join propagator per right leaf
+    assert c["S1"] == levels(j - 1) + levels(P - j - 1) + math.factorial(P) // math.factorial(j)
+
+
+@pytest.mark.parametrize("n,sqrt_s,mask", [(1, 3.0, 0), (2, 5.0, 0b11111), (3, 8.0, 0), (3, 8.0, 0b111111)])
+def test_reduced_equals_unreduced_and_oracle(n, sqrt_s, mask):
+    N = 40
+    u, hel = inputs.rambo_inputs(17, n, N, with_helicities=True)
+    mom = O.momenta_from_uniforms(u, sqrt_s, n).numpy()
+    a = Q.graph_interpret(n, mom, hel, enum_mask=mask, reduced=False)
+    b = Q.graph_interpret(n, mom, hel, enum_mask=mask, reduced=True)
+    assert np.max(np.abs(a / b - 1)) < 1e-13
+    proc = O.Process(n)
+    if mask == (1 << (n + 3)) - 1:
+        ref = O.m2_sum(O.torch.as_tensor(mom), proc).numpy()
+    else:
+        # bits outside mask come from hel; bits inside are summed
+        tot = np.zeros(N)
+        for sub in range(1 << bin(mask).count("1")):
+            h = hel.astype(np.int64) & ~mask
+            k = 0
+            for b_ in range(n + 3):
+                if (mask >> b_) & 1:
+                    h |= ((sub >> k) & 1) << b_
+                    k += 1
+            A = O.amplitudes(O.torch.as_tensor(mom), O.torch.as_tensor(h).reshape(-1, 1), proc)[:, 0].numpy()
+            tot += np.abs(A) ** 2
+        ref = tot
+    scale = O.m2_sum(O.torch.as_tensor(mom), proc).numpy() / (1 << (n + 3))
+    assert np.max(np.abs(b - ref) / np.maximum(ref, 1e-3 * scale)) < 1e-11
+
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (2, 7), (3, 3), (3, 11)])
+def test_reduction_fixpoint_is_order_independent(n, seed):
+    a, b, steps = Q.reduction_check(n, seed)
+    assert a == b and len(a) > 0
+    assert steps > 0
+
+
+def test_reduction_lowers_compute_effort():
+    """C(DAG) drops by node reduction; the drop grows with n (Sec. III-D/E)."""
+    ratios = []
+    for n in (2, 3, 4, 5):
+        cu, du = Q.graph_metrics(n, reduced=False)
+        cr, dr = Q.graph_metrics(n, reduced=True)
+        assert cr < cu
+        ratios.append(cu / cr)
+    assert all(b > a for a, b in zip(ratios, ratios[1:]))
+    c1, _ = Q.graph_metrics(1, reduced=False, split=1)
+    c1r, _ = Q.graph_metrics(1, reduced=True, split=1)
+    assert abs(c1 / c1r - 1) < 1e-12
+
+
+def test_invalid_arguments_are_rejected():
+    from paper_2511_19456_amd._lib import QedError
+    with pytest.raises(QedError):
+        Q.graph_counts(0)
+    with pytest.raises(QedError):
+        Q.graph_counts(3, split=4)
+    with pytest.raises(QedError):
+        Q.graph_counts(2, enum_mask=1 << 9)

@@ -189,6 +189,17 @@ qed_status qed_graph_metrics(int n, int n_in, uint32_t enum_mask, int split, int
 qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant, int with_aux,
                         double* compile_ms);
 
+/* Host references of the gradient pieces (no GPU), for tests:
+ * qed_graph_grad_interpret: F = log(sum over all configurations of |A|^2) and
+ * dF/dmom by a reverse sweep over the graph in float64.  mom host [N][4(n+3)]
+ * point-major; val [N]; gmom [N][4(n+3)] (rows of the incoming particles 0).
+ * qed_rambo_vjp_host: final-state momenta mom [N][4(n+1)] from uniforms
+ * u [N][4(n+1)], and gu [N][4(n+1)] = (dk/du)^T gk for given gk [N][4(n+1)]. */
+qed_status qed_graph_grad_interpret(int n, int split, int reduced, const double* mom, int64_t N, double* val,
+                                    double* gmom);
+qed_status qed_rambo_vjp_host(int n, const double* u, double sqrt_s, const double* gk, int64_t N, double* mom,
+                              double* gu);
+
 #ifdef __cplusplus
 }
 #endif

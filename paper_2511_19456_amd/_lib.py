@@ -68,6 +68,8 @@ SIGNATURES = {
                                 ctypes.POINTER(c_int64)]),
     "qed_prebuild": (c_int, [c_int, c_int, c_int, ctypes.POINTER(QedVariant), c_int,
                              ctypes.POINTER(c_double)]),
+    "qed_graph_grad_interpret": (c_int, [c_int, c_int, c_int, c_void_p, c_int64, c_void_p, c_void_p]),
+    "qed_rambo_vjp_host": (c_int, [c_int, c_void_p, c_double, c_void_p, c_int64, c_void_p, c_void_p]),
     "qed_graph_metrics": (c_int, [c_int, c_int, c_uint32, c_int, c_int, c_int, ctypes.POINTER(c_double),
                                   ctypes.POINTER(c_double)]),
 }

@@ -28,7 +28,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqedx.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SOURCES = ["qedx_dag.cpp", "qedx_emit.cpp", "qedx_kernels.cpp", "qedx_runtime.cpp", "qedx_batch.cpp"]
+HOST_SOURCES = ["qedx_dag.cpp", "qedx_emit.cpp", "qedx_kernels.cpp", "qedx_runtime.cpp", "qedx_batch.cpp",
+                "qedx_hosttools.cpp"]
 DEVICE_HEADERS = ["qedx_device.h", "qedx_rambo.h"]
 
 
@@ -81,8 +82,8 @@ class QedVariant(ctypes.Structure):
 # (n, mode, precision) built ahead of time: SUM 0 / PER_POINT 1; FP64 0 / FP32C 1
 DEFAULT_KERNELS = [
     (1, 0, 0), (2, 0, 0), (3, 0, 0), (4, 0, 0),
-    (1, 1, 0), (2, 1, 0), (3, 1, 0), (4, 1, 0), (5, 1, 0),
-    (3, 0, 1), (5, 1, 1),
+    (1, 1, 0), (2, 1, 0), (3, 1, 0), (4, 1, 0), (5, 1, 0), (6, 1, 0),
+    (3, 0, 1), (4, 1, 1), (5, 1, 1), (6, 1, 1),
 ]
 
 

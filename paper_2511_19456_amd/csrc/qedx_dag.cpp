@@ -616,4 +616,195 @@ double interpret(const Dag& d, const double* mom, uint32_t runtime_hel) {
   return r.z.r * r.z.r + r.z.i * r.z.i;
 }
 
+double interpret_grad(const Dag& d, const double* mom, uint32_t runtime_hel, double* gmom) {
+  const Process& pr = d.proc;
+  const size_t Nn = d.nodes.size();
+  std::vector<Val> v(Nn);
+  // forward (same as interpret)
+  for (size_t i = 0; i < Nn; ++i) {
+    const Node& n = d.nodes[i];
+    Val& o = v[i];
+    switch (n.kind) {
+      case Kind::Entry:
+        for (int mu = 0; mu < 4; ++mu) o.m[mu] = mom[4 * n.particle + mu];
+        break;
+      case Kind::Data: o = v[n.in[0]]; break;
+      case Kind::U: {
+        const double* p = v[n.in[0]].m;
+        int h = n.hel >= 0 ? n.hel : (int)((runtime_hel >> n.particle) & 1);
+        if (n.particle == pr.i_ein)
+          o.j = qx::u_in<double>(p[0], p[1], p[2], p[3], h, 1.0);
+        else if (n.particle == pr.i_eout)
+          o.j = qx::ubar_out<double>(p[0], p[1], p[2], p[3], h, 1.0);
+        else
+          o.e = qx::pol<double>(p[1], p[2], p[3], h);
+        break;
+      }
+      case Kind::V: {
+        const qx::pol3<double>& e = v[n.in[0]].e;
+        const qx::sp4<double>& J = v[n.in[1]].j;
+        o.j = n.side == 0 ? qx::vL<double>(J, e) : qx::vR<double>(J, e);
+        break;
+      }
+      case Kind::S1: {
+        qx::propq<double> q = prop_for(pr, mom, n.side, n.mask);
+        o.j = n.side == 0 ? qx::sL<double>(v[n.in[0]].j, q) : qx::sR<double>(v[n.in[0]].j, q);
+        break;
+      }
+      case Kind::S2:
+      case Kind::Dot: {
+        const Node& a = d.nodes[n.in[0]];
+        int iJ = a.side == 0 ? n.in[0] : n.in[1];
+        int iB = a.side == 0 ? n.in[1] : n.in[0];
+        qx::sp4<double> B = v[iB].j;
+        if (n.kind == Kind::S2) B = qx::sR<double>(B, prop_for(pr, mom, 1, d.nodes[iB].mask));
+        o.z = qx::dot<double>(B, v[iJ].j);
+        break;
+      }
+      case Kind::Sum:
+        o.z = {0.0, 0.0};
+        for (int p : n.in) {
+          o.z.r += v[p].z.r;
+          o.z.i += v[p].z.i;
+        }
+        break;
+      case Kind::HelSum:
+        o.r = 0.0;
+        for (int p : n.in) o.r += v[p].z.r * v[p].z.r + v[p].z.i * v[p].z.i;
+        break;
+    }
+  }
+  double M2 = 0.0;
+  for (size_t i = 0; i < Nn; ++i)
+    if (d.nodes[i].kind == Kind::Sum) M2 += v[i].z.r * v[i].z.r + v[i].z.i * v[i].z.i;
+  // reverse
+  struct Adj {
+    qx::sp4<double> w;
+    qx::cx<double> z;
+    qx::pol3<double> ge;
+  };
+  std::vector<Adj> a(Nn);
+  for (auto& x : a) {
+    x.w = qx::zero4<double>();
+    x.z = {0.0, 0.0};
+    x.ge = {0.0, 0.0, 0.0};
+  }
+  for (int k = 0; k < 4 * pr.npart; ++k) gmom[k] = 0.0;
+  auto fixed = [&](int particle) { return particle == pr.i_ein || particle == 1; };
+  auto add_prop_grad = [&](int side, uint32_t mask, const qx::propq<double>& gq) {
+    double K[4] = {0, 0, 0, 0};
+    for (int b = 0; b < pr.P; ++b)
+      if ((mask >> b) & 1) {
+        const double* kk = mom + 4 * pr.photon_particle[b];
+        for (int mu = 0; mu < 4; ++mu) K[mu] += pr.photon_sign[b] * kk[mu];
+      }
+    int pe = side == 0 ? pr.i_ein : pr.i_eout;
+    const double* p = mom + 4 * pe;
+    double gp[4] = {0, 0, 0, 0}, gK[4] = {0, 0, 0, 0};
+    qx::prop_from_vjp(p[0], p[1], p[2], p[3], K[0], K[1], K[2], K[3], side == 0 ? 1.0 : -1.0, 1.0, gq, gp, gK);
+    if (!fixed(pe))
+      for (int mu = 0; mu < 4; ++mu) gmom[4 * pe + mu] += gp[mu];
+    for (int b = 0; b < pr.P; ++b)
+      if ((mask >> b) & 1) {
+        int part = pr.photon_particle[b];
+        if (!(pr.photon_sign[b] > 0 && part == 1))
+          for (int mu = 0; mu < 4; ++mu) gmom[4 * part + mu] += pr.photon_sign[b] * gK[mu];
+      }
+  };
+  for (size_t ii = Nn; ii-- > 0;) {
+    const Node& n = d.nodes[ii];
+    Adj& w = a[ii];
+    switch (n.kind) {
+      case Kind::HelSum:
+        break;
+      case Kind::Sum: {
+        qx::cx<double> c = {v[ii].z.r / M2, -v[ii].z.i / M2};
+        for (int p : n.in) {
+          a[p].z.r += c.r;
+          a[p].z.i += c.i;
+        }
+        break;
+      }
+      case Kind::Data: {
+        int p = n.in[0];
+        qx::add_to(a[p].w, w.w);
+        a[p].z.r += w.z.r;
+        a[p].z.i += w.z.i;
+        a[p].ge.e1 += w.ge.e1;
+        a[p].ge.e2 += w.ge.e2;
+        a[p].ge.e3 += w.ge.e3;
+        break;
+      }
+      case Kind::S2:
+      case Kind::Dot: {
+        const Node& an = d.nodes[n.in[0]];
+        int iJ = an.side == 0 ? n.in[0] : n.in[1];
+        int iB = an.side == 0 ? n.in[1] : n.in[0];
+        qx::sp4<double> B = v[iB].j;
+        qx::propq<double> q{};
+        if (n.kind == Kind::S2) {
+          q = prop_for(pr, mom, 1, d.nodes[iB].mask);
+          B = qx::sR<double>(B, q);
+        }
+        qx::sp4<double> wB = qx::zero4<double>();
+        qx::dot_vjp(w.z, B, v[iJ].j, wB, a[iJ].w);
+        if (n.kind == Kind::S2) {
+          qx::add_to(a[iB].w, qx::sL<double>(wB, q));
+          qx::propq<double> gq = {0, 0, 0, 0, 0};
+          qx::sR_gq(wB, v[iB].j, gq);
+          add_prop_grad(1, d.nodes[iB].mask, gq);
+        } else {
+          qx::add_to(a[iB].w, wB);
+        }
+        break;
+      }
+      case Kind::S1: {
+        qx::propq<double> q = prop_for(pr, mom, n.side, n.mask);
+        qx::propq<double> gq = {0, 0, 0, 0, 0};
+        const qx::sp4<double>& J = v[n.in[0]].j;
+        if (n.side == 0) {
+          qx::add_to(a[n.in[0]].w, qx::sR<double>(w.w, q));
+          qx::sL_gq(w.w, J, gq);
+        } else {
+          qx::add_to(a[n.in[0]].w, qx::sL<double>(w.w, q));
+          qx::sR_gq(w.w, J, gq);
+        }
+        add_prop_grad(n.side, n.mask, gq);
+        break;
+      }
+      case Kind::V: {
+        const qx::pol3<double>& e = v[n.in[0]].e;
+        const qx::sp4<double>& J = v[n.in[1]].j;
+        qx::pol3<double>& ge = a[n.in[0]].ge;
+        if (n.side == 0) {
+          qx::add_to(a[n.in[1]].w, qx::vR<double>(w.w, e));
+          qx::vL_ge(w.w, J, ge);
+        } else {
+          qx::add_to(a[n.in[1]].w, qx::vL<double>(w.w, e));
+          qx::vR_ge(w.w, J, ge);
+        }
+        break;
+      }
+      case Kind::U: {
+        int part = n.particle;
+        if (fixed(part)) break;
+        const double* p = v[n.in[0]].m;
+        int h = n.hel >= 0 ? n.hel : (int)((runtime_hel >> n.particle) & 1);
+        if (part == pr.i_eout) {
+          double g[4];
+          qx::ubar_vjp(p[0], p[1], p[2], p[3], h, 1.0, w.w, g);
+          for (int mu = 0; mu < 4; ++mu) gmom[4 * part + mu] += g[mu];
+        } else {
+          double g[3];
+          qx::pol_vjp(p[1], p[2], p[3], h, w.ge, g);
+          for (int mu = 0; mu < 3; ++mu) gmom[4 * part + 1 + mu] += g[mu];
+        }
+        break;
+      }
+      default: break;
+    }
+  }
+  return log(M2);
+}
+
 }  // namespace qedx

@@ -107,4 +107,9 @@ double data_transfer(const Dag& d, bool fp32);
 // runtime_hel gives the state of every particle not enumerated.
 double interpret(const Dag& d, const double* mom, uint32_t runtime_hel);
 
+// Host reverse-mode reference: F = log(value of the exit) and dF/dmom for the
+// momenta of the final-state particles (e-_out and outgoing photons; the
+// incoming momenta are treated as fixed, their rows stay 0).
+double interpret_grad(const Dag& d, const double* mom, uint32_t runtime_hel, double* gmom);
+
 }  // namespace qedx

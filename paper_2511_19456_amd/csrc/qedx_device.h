@@ -268,4 +268,165 @@ QEDX_HD propq<T> prop_from(double p0, double p1, double p2, double p3, double K0
   return prop_coeffs<T>(p0 + s * K0, p1 + s * K1, p2 + s * K2, p3 + s * K3, D, m);
 }
 
+// ---------------------------------------------------------------------------
+// Vector-Jacobian products for the adjoint (reverse) sweep.
+//
+// For a complex intermediate z the adjoint weight w is defined by
+//   dF = 2 Re sum_k w_k dz_k,
+// so for F = log(sum_h |A_h|^2) the seed of amplitude A_h is conj(A_h)/|M|^2.
+// A linear map J' = M J then gives w_J += M^T w_J' (transpose, no conjugate),
+// which for the slash-type maps here is the same map applied from the other
+// side: adjoint of vL is vR, of sL is sR and vice versa.
+// ---------------------------------------------------------------------------
+template <class T> QEDX_HD void add_to(sp4<T>& w, const sp4<T>& x) {
+  for (int k = 0; k < 4; ++k) {
+    w.c[k].r = w.c[k].r + x.c[k].r;
+    w.c[k].i = w.c[k].i + x.c[k].i;
+  }
+}
+template <class T> QEDX_HD sp4<T> zero4() {
+  sp4<T> z;
+  for (int k = 0; k < 4; ++k) z.c[k] = {T(0), T(0)};
+  return z;
+}
+// w += c * x (complex scalar times spinor)
+template <class T> QEDX_HD void axpy(sp4<T>& w, const cx<T>& c, const sp4<T>& x) {
+  for (int k = 0; k < 4; ++k) {
+    w.c[k].r = w.c[k].r + c.r * x.c[k].r - c.i * x.c[k].i;
+    w.c[k].i = w.c[k].i + c.r * x.c[k].i + c.i * x.c[k].r;
+  }
+}
+// Dot A = sum_k B_k J_k with seed c: w_B += c J, w_J += c B.
+template <class T> QEDX_HD void dot_vjp(const cx<T>& c, const sp4<T>& B, const sp4<T>& J, sp4<T>& wB, sp4<T>& wJ) {
+  axpy(wB, c, J);
+  axpy(wJ, c, B);
+}
+// 2 Re(x^T sigma_i y) for the three Pauli matrices, x, y 2-spinors.
+template <class T> QEDX_HD void re_pauli(const cx<T>& x0, const cx<T>& x1, const cx<T>& y0, const cx<T>& y1, T s,
+                                         T& g1, T& g2, T& g3) {
+  // sigma1: x0 y1 + x1 y0; sigma2: -i x0 y1 + i x1 y0; sigma3: x0 y0 - x1 y1
+  T a01r = x0.r * y1.r - x0.i * y1.i, a01i = x0.r * y1.i + x0.i * y1.r;
+  T a10r = x1.r * y0.r - x1.i * y0.i, a10i = x1.r * y0.i + x1.i * y0.r;
+  T a00r = x0.r * y0.r - x0.i * y0.i;
+  T a11r = x1.r * y1.r - x1.i * y1.i;
+  g1 = g1 + s * T(2) * (a01r + a10r);
+  g2 = g2 + s * T(2) * (a01i - a10i);  // Re(-i z) = Im z
+  g3 = g3 + s * T(2) * (a00r - a11r);
+}
+// Polarisation gradient of a left vertex J' = (-E R, E L), E = e . sigma:
+// 2 Re(w . J') = 2 Re(-wa^T E R + wb^T E L).
+template <class T> QEDX_HD void vL_ge(const sp4<T>& w, const sp4<T>& J, pol3<T>& g) {
+  re_pauli(w.c[0], w.c[1], J.c[2], J.c[3], T(-1), g.e1, g.e2, g.e3);
+  re_pauli(w.c[2], w.c[3], J.c[0], J.c[1], T(1), g.e1, g.e2, g.e3);
+}
+// Right vertex Jb' = (b E, -a E): 2 Re(b^T E wa - a^T E wb).
+template <class T> QEDX_HD void vR_ge(const sp4<T>& w, const sp4<T>& J, pol3<T>& g) {
+  re_pauli(J.c[2], J.c[3], w.c[0], w.c[1], T(1), g.e1, g.e2, g.e3);
+  re_pauli(J.c[0], J.c[1], w.c[2], w.c[3], T(-1), g.e1, g.e2, g.e3);
+}
+template <class T> QEDX_HD T re_mul(const cx<T>& a, const cx<T>& b) { return a.r * b.r - a.i * b.i; }
+template <class T> QEDX_HD T im_mul(const cx<T>& a, const cx<T>& b) { return a.r * b.i + a.i * b.r; }
+// Propagator-coefficient gradient of a left S1: J' = (mm L + Qs R, Qb L + mm R).
+template <class T> QEDX_HD void sL_gq(const sp4<T>& w, const sp4<T>& J, propq<T>& g) {
+  const cx<T>&a0 = w.c[0], &a1 = w.c[1], &b0 = w.c[2], &b1 = w.c[3];
+  const cx<T>&L0 = J.c[0], &L1 = J.c[1], &R0 = J.c[2], &R1 = J.c[3];
+  g.mm = g.mm + T(2) * (re_mul(a0, L0) + re_mul(a1, L1) + re_mul(b0, R0) + re_mul(b1, R1));
+  g.qm = g.qm + T(2) * (re_mul(a0, R0) + re_mul(b1, L1));
+  g.qp = g.qp + T(2) * (re_mul(a1, R1) + re_mul(b0, L0));
+  g.q1 = g.q1 + T(2) * (-re_mul(a0, R1) - re_mul(a1, R0) + re_mul(b0, L1) + re_mul(b1, L0));
+  // Re(i z) = -Im z
+  g.q2 = g.q2 + T(2) * (-im_mul(a0, R1) + im_mul(a1, R0) + im_mul(b0, L1) - im_mul(b1, L0));
+}
+// Right S1: Jb' = (mm a + b Qb, a Qs + mm b) with w = (wa, wb), J = (a, b).
+template <class T> QEDX_HD void sR_gq(const sp4<T>& w, const sp4<T>& J, propq<T>& g) {
+  const cx<T>&wa0 = w.c[0], &wa1 = w.c[1], &wb0 = w.c[2], &wb1 = w.c[3];
+  const cx<T>&a0 = J.c[0], &a1 = J.c[1], &b0 = J.c[2], &b1 = J.c[3];
+  g.mm = g.mm + T(2) * (re_mul(wa0, a0) + re_mul(wa1, a1) + re_mul(wb0, b0) + re_mul(wb1, b1));
+  g.qm = g.qm + T(2) * (re_mul(b1, wa1) + re_mul(a0, wb0));
+  g.qp = g.qp + T(2) * (re_mul(b0, wa0) + re_mul(a1, wb1));
+  g.q1 = g.q1 + T(2) * (re_mul(b0, wa1) + re_mul(b1, wa0) - re_mul(a0, wb1) - re_mul(a1, wb0));
+  g.q2 = g.q2 + T(2) * (im_mul(b0, wa1) - im_mul(b1, wa0) - im_mul(a0, wb1) + im_mul(a1, wb0));
+}
+// Gradient of 2 Re(w . ubar(p, s)) with respect to p = (E, px, py, pz).
+QEDX_HD void ubar_vjp(double E, double px, double py, double pz, int s, double m, const sp4<double>& w,
+                      double g[4]) {
+  // ubar = (conj psi_R, conj psi_L); psi components are nrm * (affine in p),
+  // nrm = (2c)^(-1/2), c = E + m.  Write u_k = nrm * v_k(p); then
+  // d u_k = nrm dv_k + v_k dnrm, dnrm/dE = -nrm / (2c).
+  double c = E + m;
+  double nrm = 1.0 / sqrt(2.0 * c);
+  double dn = -nrm / (2.0 * c);
+  // v for psi_L (index 0,1) and psi_R (index 2,3) as complex (re, im);
+  // dv/dp columns: E, px, py, pz
+  double vr[4], vi[4], dvr[4][4], dvi[4][4];
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 4; ++j) dvr[k][j] = dvi[k][j] = 0.0;
+  if (s == 0) {
+    vr[0] = c - pz; vi[0] = 0;   dvr[0][0] = 1; dvr[0][3] = -1;
+    vr[1] = -px;    vi[1] = -py; dvr[1][1] = -1; dvi[1][2] = -1;
+    vr[2] = c + pz; vi[2] = 0;   dvr[2][0] = 1; dvr[2][3] = 1;
+    vr[3] = px;     vi[3] = py;  dvr[3][1] = 1; dvi[3][2] = 1;
+  } else {
+    vr[0] = -px;    vi[0] = py;  dvr[0][1] = -1; dvi[0][2] = 1;
+    vr[1] = c + pz; vi[1] = 0;   dvr[1][0] = 1; dvr[1][3] = 1;
+    vr[2] = px;     vi[2] = -py; dvr[2][1] = 1; dvi[2][2] = -1;
+    vr[3] = c - pz; vi[3] = 0;   dvr[3][0] = 1; dvr[3][3] = -1;
+  }
+  // ubar component k = conj(u_{perm k}), perm = (2,3,0,1)
+  const int perm[4] = {2, 3, 0, 1};
+  for (int j = 0; j < 4; ++j) g[j] = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    int q = perm[k];
+    // d(conj u_q) = nrm conj(dv_q) + conj(v_q) dnrm
+    for (int j = 0; j < 4; ++j) {
+      double dr = nrm * dvr[q][j] + (j == 0 ? vr[q] * dn : 0.0);
+      double di = -(nrm * dvi[q][j] + (j == 0 ? vi[q] * dn : 0.0));
+      g[j] += 2.0 * (w.c[k].r * dr - w.c[k].i * di);
+    }
+  }
+}
+// Gradient of ge . eps(k, lam) with respect to (kx, ky, kz).
+QEDX_HD void pol_vjp(double kx, double ky, double kz, int lam, const pol3<double>& ge, double g[3]) {
+  double kt2 = kx * kx + ky * ky;
+  double kt = sqrt(kt2);
+  double kk2 = kt2 + kz * kz;
+  double kk = sqrt(kk2);
+  g[0] = g[1] = g[2] = 0.0;
+  if (!(kt > 0.0)) return;  // measure-zero direction; derivative not defined
+  double cf = kx / kt, sf = ky / kt, ct = kz / kk, st = kt / kk;
+  double kt3 = kt2 * kt, kk3 = kk2 * kk;
+  // partial derivatives of cf, sf, ct, st
+  double dcf[3] = {ky * ky / kt3, -kx * ky / kt3, 0.0};
+  double dsf[3] = {-kx * ky / kt3, kx * kx / kt3, 0.0};
+  double dct[3] = {-kz * kx / kk3, -kz * ky / kk3, kt2 / kk3};
+  double dst[3] = {cf * kz * kz / kk3, sf * kz * kz / kk3, -kt * kz / kk3};
+  for (int j = 0; j < 3; ++j) {
+    if (lam == 0)  // (ct cf, ct sf, -st)
+      g[j] = ge.e1 * (dct[j] * cf + ct * dcf[j]) + ge.e2 * (dct[j] * sf + ct * dsf[j]) - ge.e3 * dst[j];
+    else  // (-sf, cf, 0)
+      g[j] = -ge.e1 * dsf[j] + ge.e2 * dcf[j];
+  }
+}
+// Gradient through prop_from: given g over (qm, qp, q1, q2, mm), accumulate
+// into gp (the electron momentum) and gK (the photon sum).
+QEDX_HD void prop_from_vjp(double p0, double p1, double p2, double p3, double K0, double K1, double K2, double K3,
+                           double s, double m, const propq<double>& g, double gp[4], double gK[4]) {
+  double pK = p0 * K0 - p1 * K1 - p2 * K2 - p3 * K3;
+  double KK = K0 * K0 - K1 * K1 - K2 * K2 - K3 * K3;
+  double D = 2.0 * s * pK + KK;
+  double id = 1.0 / D;
+  double Q0 = p0 + s * K0, Q1 = p1 + s * K1, Q2 = p2 + s * K2, Q3 = p3 + s * K3;
+  double gQ0 = (g.qm + g.qp) * id, gQ3 = (g.qp - g.qm) * id, gQ1 = g.q1 * id, gQ2 = g.q2 * id;
+  double gid = g.qm * (Q0 - Q3) + g.qp * (Q0 + Q3) + g.q1 * Q1 + g.q2 * Q2 + g.mm * m;
+  double gD = -gid * id * id;
+  const double eta[4] = {1.0, -1.0, -1.0, -1.0};
+  const double gQ[4] = {gQ0, gQ1, gQ2, gQ3};
+  const double pp[4] = {p0, p1, p2, p3};
+  const double KKv[4] = {K0, K1, K2, K3};
+  for (int mu = 0; mu < 4; ++mu) {
+    gp[mu] += gQ[mu] + gD * 2.0 * s * eta[mu] * KKv[mu];
+    gK[mu] += s * gQ[mu] + gD * (2.0 * s * eta[mu] * pp[mu] + 2.0 * eta[mu] * KKv[mu]);
+  }
+}
+
 }  // namespace qx

@@ -64,6 +64,18 @@ struct Emitter {
   EmitStats st;
   std::string T;
   std::string ind = "  ";
+  int mom_src = 0;  // 0: reload momenta from global memory; 1: opaque copies of registers M<p>_<mu>
+  // Partition loop: one block for the canonical partition (photons 0..split-1
+  // on the e-_in side) inside a run-time loop over all partitions; photon
+  // slot a of iteration `it` is particle slot_tab[it][a], loaded per iteration.
+  bool slot = false;
+  std::string slot_tab;
+
+  int slot_of(int particle) const {
+    for (int a = 0; a < pr.P; ++a)
+      if (pr.photon_particle[a] == particle) return a;
+    return -1;
+  }
 
   Emitter(const Dag& d_, const Variant& v_) : d(d_), v(v_), pr(d_.proc), done(d_.nodes.size(), 0) {
     T = v.prec == PREC_F64 ? "double" : "float";
@@ -80,7 +92,11 @@ struct Emitter {
     int lo = __builtin_ctz(mask);
     uint32_t rest = mask & (mask - 1);
     std::string km = "K" + std::to_string(mask);
-    if (rest == 0) {
+    if (rest == 0 && slot) {
+      for (int mu = 0; mu < 4; ++mu)
+        os << ind << "const double " << km << "_" << mu << " = sg" << lo << " * k" << lo << "_" << mu << ";\n";
+      st.flops_per_point += 4;
+    } else if (rest == 0) {
       int part = pr.photon_particle[lo];
       const char* sg = pr.photon_sign[lo] > 0 ? "" : "-";
       for (int mu = 0; mu < 4; ++mu)
@@ -116,10 +132,11 @@ struct Emitter {
 
   std::string hel_expr(const Node& u) const {
     if (u.hel >= 0) return std::to_string((int)u.hel);
+    if (slot && slot_of(u.particle) >= 0) return "hb" + std::to_string(slot_of(u.particle));
     return "(int)((hc >> " + std::to_string(u.particle) + ") & 1u)";
   }
 
-  bool local() const { return (v.order & 4) != 0; }
+  bool local() const { return (v.order & 4) != 0 && !slot; }
 
   // scheduling fence: keeps LLVM's machine scheduler from moving work across
   void fence(int level) {
@@ -143,9 +160,11 @@ struct Emitter {
         else if (p == pr.i_eout)
           os << ind << "const qx::sp4<" << T << "> " << nm << " = qx::ubar_out<" << T << ">(" << m << "0, " << m
              << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", 1.0);\n";
-        else
+        else {
+          if (slot) m = "k" + std::to_string(slot_of(p)) + "_";
           os << ind << "const qx::pol3<" << T << "> " << nm << " = qx::pol<" << T << ">(" << m << "1, " << m << "2, "
              << m << "3, " << hel_expr(n) << ");\n";
+        }
         st.flops_per_point += 16;
         ++st.n_U;
         break;
@@ -202,29 +221,24 @@ struct Emitter {
     fence(2);
   }
 
-  // Body: accumulators, all nodes in partition-grouped order, |A|^2 sums
-  // added into the double `acc` of the enclosing scope.
-  void body() {
-    std::vector<int> sums, dots;
-    for (size_t i = 0; i < d.nodes.size(); ++i) {
+  std::vector<int> sum_nodes() const {
+    std::vector<int> sums;
+    for (size_t i = 0; i < d.nodes.size(); ++i)
       if (d.nodes[i].kind == Kind::Sum) sums.push_back((int)i);
-      if (d.nodes[i].kind == Kind::Dot) dots.push_back((int)i);
-    }
-    for (size_t a = 0; a < sums.size(); ++a) {
-      acc_of_sum[sums[a]] = (int)a;
-      os << ind << "qx::cx<" << T << "> A" << a << " = {" << T << "(0), " << T << "(0)};\n";
-      if (v.prec != PREC_F64) os << ind << "qx::cx<float> C" << a << " = {0.0f, 0.0f};\n";
-    }
-    // group dots by the photon set on the e-_in side
-    std::map<uint32_t, std::vector<int>> part;
-    for (int k : dots) {
-      auto ops = dot_ops(d.nodes[k]);
-      part[d.nodes[producer(ops.first)].mask].push_back(k);
-    }
-    // order partitions greedily by overlap with the previous one
+    return sums;
+  }
+
+  // Dots grouped by the photon set on the e-_in side (one group per
+  // partition), and an order of the groups in which consecutive partitions
+  // share as many photons as possible.
+  void partitions(std::map<uint32_t, std::vector<int>>& part, std::vector<uint32_t>& order) const {
+    for (size_t i = 0; i < d.nodes.size(); ++i)
+      if (d.nodes[i].kind == Kind::Dot) {
+        auto ops = dot_ops(d.nodes[i]);
+        part[d.nodes[producer(ops.first)].mask].push_back((int)i);
+      }
     std::vector<uint32_t> keys;
     for (auto& kv : part) keys.push_back(kv.first);
-    std::vector<uint32_t> order;
     std::vector<char> used(keys.size(), 0);
     uint32_t cur = keys.empty() ? 0 : keys[0];
     for (size_t t = 0; t < keys.size(); ++t) {
@@ -241,48 +255,129 @@ struct Emitter {
       cur = keys[best];
       order.push_back(cur);
     }
-    for (uint32_t key : order) {
-      std::vector<int>& dk = part[key];
-      std::set<int> Bs, Js;
+  }
+
+  // Partition-local block: momenta reloaded through a value the compiler
+  // cannot see through, so nothing computed here is merged with (and kept
+  // live from) another partition's block; a uniform branch on an opaque flag
+  // puts the block in its own basic block, so instruction selection
+  // schedules it on its own.
+  std::string open_block() {
+    std::string outer = ind;
+    os << ind << "{\n" << ind << "  int live = 1;\n" << ind << "  asm volatile(\"\" : \"+s\"(live));\n" << ind
+       << "  if (live) {\n";
+    ind += "    ";
+    block_momenta();
+    std::fill(done.begin(), done.end(), 0);
+    kdone.clear();
+    qdone.clear();
+    return outer;
+  }
+  void close_block(const std::string& outer) {
+    ind = outer;
+    os << ind << "  }\n" << ind << "}\n";
+  }
+
+  void forward_block(uint32_t key, const std::vector<int>& dk) {
+    fence(1);
+    os << ind << "// photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << " on the e-_in | e-_out side\n";
+    std::string outer;
+    if (local()) outer = open_block();
+    forward_block_inner(key, dk);
+    if (local()) close_block(outer);
+  }
+
+  void forward_block_inner(uint32_t key, const std::vector<int>& dk) {
+    (void)key;
+    std::set<int> Bs, Js;
+    for (int k : dk) {
+      auto ops = dot_ops(d.nodes[k]);
+      Js.insert(producer(ops.first));
+      Bs.insert(producer(ops.second));
+    }
+    bool holdB = Bs.size() <= Js.size();
+    const std::set<int>& hold = holdB ? Bs : Js;
+    const std::set<int>& stream = holdB ? Js : Bs;
+    for (int h : hold) emit(h);
+    for (int s : stream) {
+      emit(s);
       for (int k : dk) {
         auto ops = dot_ops(d.nodes[k]);
-        Js.insert(producer(ops.first));
-        Bs.insert(producer(ops.second));
+        int sp = producer(holdB ? ops.first : ops.second);
+        if (sp == s) emit_dot(k);
       }
-      bool holdB = Bs.size() <= Js.size();
-      const std::set<int>& hold = holdB ? Bs : Js;
-      const std::set<int>& stream = holdB ? Js : Bs;
-      fence(1);
-      os << ind << "// photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << " on the e-_in | e-_out side\n";
-      std::string outer = ind;
-      if (local()) {
-        // Partition-local block: momenta reloaded through an index the
-        // compiler cannot see through, so nothing computed here is merged
-        // with (and kept live from) another partition's block.
-        // A uniform branch on an opaque flag puts the block in its own basic
-        // block, so instruction selection schedules it on its own.
-        os << ind << "{\n" << ind << "  int live = 1;\n" << ind << "  asm volatile(\"\" : \"+s\"(live));\n"
-           << ind << "  if (live) {\n";
-        ind += "    ";
-        os << ind << "long long pq = ptc;\n" << ind << "asm volatile(\"\" : \"+v\"(pq));\n";
-        load_momenta("mom", "N", "pq");
-        std::fill(done.begin(), done.end(), 0);
-        kdone.clear();
-        qdone.clear();
-      }
-      for (int h : hold) emit(h);
-      for (int s : stream) {
-        emit(s);
-        for (int k : dk) {
-          auto ops = dot_ops(d.nodes[k]);
-          int sp = producer(holdB ? ops.first : ops.second);
-          if (sp == s) emit_dot(k);
-        }
-      }
-      if (local()) {
-        ind = outer;
-        os << ind << "  }\n" << ind << "}\n";
-      }
+    }
+  }
+
+  // The partitions of the photons into the two sides of the joins, in the
+  // slot order used by slot_loop: iteration t puts photons subsets[t] on the
+  // e-_in side; returns the table of particle indices [NIT][P].
+  std::vector<int> slot_table() const {
+    const int P = pr.P, j = d.split;
+    std::vector<int> tab;
+    for (uint32_t m = 0; m < (1u << P); ++m) {
+      if (popc(m) != j) continue;
+      for (int a = 0; a < P; ++a)
+        if ((m >> a) & 1) tab.push_back(pr.photon_particle[a]);
+      for (int a = 0; a < P; ++a)
+        if (!((m >> a) & 1)) tab.push_back(pr.photon_particle[a]);
+    }
+    return tab;
+  }
+
+  void emit_slot_table() {
+    std::vector<int> tab = slot_table();
+    os << "__constant__ int " << slot_tab << "[" << tab.size() << "] = {";
+    for (size_t i = 0; i < tab.size(); ++i) os << (i ? ", " : "") << tab[i];
+    os << "};\n";
+  }
+
+  void slot_loop(std::map<uint32_t, std::vector<int>>& part) {
+    const int P = pr.P;
+    const uint32_t key = (1u << d.split) - 1;
+    const int nit = (int)(slot_table().size() / P);
+    if (!part.count(key)) throw std::logic_error("canonical partition missing");
+    for (int p : {pr.i_ein, pr.i_eout})
+      for (int mu = 0; mu < 4; ++mu)
+        os << ind << "const double m" << p << "_" << mu << " = mom[" << (4 * p + mu) << " * N + ptc];\n";
+    os << ind << "#pragma unroll 1\n" << ind << "for (int it = 0; it < " << nit << "; ++it) {\n";
+    std::string outer = ind;
+    ind += "  ";
+    for (int a = 0; a < P; ++a) {
+      os << ind << "const int sp" << a << " = " << slot_tab << "[it * " << P << " + " << a << "];\n";
+      os << ind << "const double sg" << a << " = sp" << a << " < " << pr.i_eout << " ? 1.0 : -1.0;\n";
+      os << ind << "const int hb" << a << " = (int)((hc >> sp" << a << ") & 1u);\n";
+      for (int mu = 0; mu < 4; ++mu)
+        os << ind << "const double k" << a << "_" << mu << " = mom[(4 * sp" << a << " + " << mu << ") * N + ptc];\n";
+    }
+    std::fill(done.begin(), done.end(), 0);
+    kdone.clear();
+    qdone.clear();
+    double f0 = st.flops_per_point;
+    bool was_local = (v.order & 4) != 0;
+    (void)was_local;
+    forward_block_inner(key, part[key]);
+    st.flops_per_point = f0 + (st.flops_per_point - f0) * nit;
+    ind = outer;
+    os << ind << "}\n";
+  }
+
+  // Body: accumulators, all nodes in partition-grouped order, |A|^2 sums
+  // added into the double `acc` of the enclosing scope.
+  void body() {
+    std::vector<int> sums = sum_nodes();
+    for (size_t a = 0; a < sums.size(); ++a) {
+      acc_of_sum[sums[a]] = (int)a;
+      os << ind << "qx::cx<" << T << "> A" << a << " = {" << T << "(0), " << T << "(0)};\n";
+      if (v.prec != PREC_F64) os << ind << "qx::cx<float> C" << a << " = {0.0f, 0.0f};\n";
+    }
+    std::map<uint32_t, std::vector<int>> part;
+    std::vector<uint32_t> order;
+    partitions(part, order);
+    if (slot) {
+      slot_loop(part);
+    } else {
+      for (uint32_t key : order) forward_block(key, part[key]);
     }
     // |A|^2, summed over the enumerated configurations (HelSum) or single
     for (size_t a = 0; a < sums.size(); ++a) {
@@ -293,6 +388,182 @@ struct Emitter {
            << ".i + (double)C" << a << ".i; acc += ar * ar + ai * ai; }\n";
       }
       st.flops_per_point += 4;
+    }
+  }
+
+  // ---------------------------------------------------------------------
+  // Adjoint pass.  Per partition block: the e-_in-side leaves are recomputed
+  // and held; the e-_out-side prefix trie is walked depth first, recomputing
+  // each current from its parent, taking the dots at its leaves and folding
+  // each node's adjoint into its parent on the way back; then the e-_in-side
+  // trie is walked the same way with the leaf adjoints gathered at the dots.
+  // Only the current path is live: currents are recomputed, not stored.
+  // ---------------------------------------------------------------------
+  std::set<int> blk;
+  std::map<int, std::vector<int>> cons;
+  std::set<int> leafJ;
+
+  bool final_particle(int p) const { return p == pr.i_eout || (p > pr.i_eout); }
+
+  void collect_block(const std::vector<int>& dk) {
+    blk.clear();
+    cons.clear();
+    std::vector<int> stk(dk.begin(), dk.end());
+    while (!stk.empty()) {
+      int x = stk.back();
+      stk.pop_back();
+      if (blk.count(x)) continue;
+      blk.insert(x);
+      for (int p : d.nodes[x].in) {
+        int pp = producer(p);
+        if (d.nodes[pp].kind == Kind::Entry) continue;
+        cons[pp].push_back(x);
+        stk.push_back(pp);
+      }
+    }
+  }
+
+  std::string fname(int x) const { return (done[x] ? "n" : "f") + std::to_string(x); }
+
+  void emit_K_inline(uint32_t mask) {
+    for (int mu = 0; mu < 4; ++mu) {
+      os << ind << "const double Kl" << mu << " = 0.0";
+      for (int a = 0; a < pr.P; ++a)
+        if ((mask >> a) & 1)
+          os << (pr.photon_sign[a] > 0 ? " + " : " - ") << "m" << pr.photon_particle[a] << "_" << mu;
+      os << ";\n";
+    }
+  }
+
+  void prop_grad_to_momenta(int side, uint32_t mask) {
+    int pe = side == 0 ? pr.i_ein : pr.i_eout;
+    std::string m = "m" + std::to_string(pe) + "_";
+    os << ind << "{ double gp[4] = {0.0, 0.0, 0.0, 0.0}, gK[4] = {0.0, 0.0, 0.0, 0.0};\n";
+    os << ind << "  qx::prop_from_vjp(" << m << "0, " << m << "1, " << m << "2, " << m << "3, Kl0, Kl1, Kl2, Kl3, "
+       << (side == 0 ? "1.0" : "-1.0") << ", 1.0, gq, gp, gK);\n";
+    if (final_particle(pe))
+      for (int mu = 0; mu < 4; ++mu) os << ind << "  gm" << pe << "_" << mu << " += gp[" << mu << "];\n";
+    for (int a = 0; a < pr.P; ++a)
+      if (((mask >> a) & 1) && final_particle(pr.photon_particle[a]))
+        for (int mu = 0; mu < 4; ++mu)
+          os << ind << "  gm" << pr.photon_particle[a] << "_" << mu << (pr.photon_sign[a] > 0 ? " += " : " -= ")
+             << "gK[" << mu << "];\n";
+    os << ind << "}\n";
+  }
+
+  // Emit the adjoint contribution of consumer c (of current x) into w<x>.
+  void rev(int c, int x) {
+    const Node& n = d.nodes[c];
+    if (n.kind == Kind::Dot) {
+      auto ops = dot_ops(n);
+      int J = producer(ops.first), B = producer(ops.second);
+      int sum = d.nodes[n.out[0]].out[0];
+      os << ind << "qx::dot_vjp<double>(c" << acc_of_sum.at(sum) << ", " << fname(B) << ", " << fname(J) << ", w" << B
+         << ", w" << J << ");\n";
+      st.flops_per_point += 64;
+      return;
+    }
+    const std::string X = fname(x);
+    os << ind << "{\n";
+    std::string outer = ind;
+    ind += "  ";
+    const bool leaf = leafJ.count(c) > 0;
+    if (n.kind == Kind::S1) {
+      emit_K_inline(n.mask);
+      int pe = n.side == 0 ? pr.i_ein : pr.i_eout;
+      std::string m = "m" + std::to_string(pe) + "_";
+      os << ind << "const qx::propq<double> q = qx::prop_from<double>(" << m << "0, " << m << "1, " << m << "2, " << m
+         << "3, Kl0, Kl1, Kl2, Kl3, " << (n.side == 0 ? "1.0" : "-1.0") << ", 1.0);\n";
+      st.flops_per_point += 28;
+    }
+    const std::string side = n.side == 0 ? "L" : "R", other = n.side == 0 ? "R" : "L";
+    std::string E;
+    if (n.kind == Kind::V) E = "n" + std::to_string(producer(n.in[0]));
+    if (!leaf) {
+      if (n.kind == Kind::V)
+        os << ind << "const qx::sp4<double> f" << c << " = qx::v" << side << "<double>(" << X << ", " << E << ");\n";
+      else
+        os << ind << "const qx::sp4<double> f" << c << " = qx::s" << side << "<double>(" << X << ", q);\n";
+      os << ind << "qx::sp4<double> w" << c << " = qx::zero4<double>();\n";
+      st.flops_per_point += n.kind == Kind::V ? 40 : 56;
+      for (int c2 : cons[c]) rev(c2, c);
+    }
+    if (n.kind == Kind::V) {
+      os << ind << "qx::add_to(w" << x << ", qx::v" << other << "<double>(w" << c << ", " << E << "));\n";
+      os << ind << "qx::v" << side << "_ge<double>(w" << c << ", " << X << ", ge" << producer(n.in[0]) << ");\n";
+      st.flops_per_point += 40 + 48;
+    } else {
+      os << ind << "qx::add_to(w" << x << ", qx::s" << other << "<double>(w" << c << ", q));\n";
+      os << ind << "qx::propq<double> gq = {0.0, 0.0, 0.0, 0.0, 0.0};\n";
+      os << ind << "qx::s" << side << "_gq<double>(w" << c << ", " << X << ", gq);\n";
+      prop_grad_to_momenta(n.side, n.mask);
+      st.flops_per_point += 56 + 64 + 60;
+    }
+    ind = outer;
+    os << ind << "}\n";
+  }
+
+  void grad_block(uint32_t key, const std::vector<int>& dk) {
+    collect_block(dk);
+    os << ind << "// adjoint: photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << "\n";
+    std::string outer = open_block();
+    // polarisation-gradient accumulators of this block
+    for (int x : blk) {
+      const Node& n = d.nodes[x];
+      if (n.kind == Kind::U && n.particle != pr.i_ein && n.particle != pr.i_eout) {
+        emit(x);
+        os << ind << "qx::pol3<double> ge" << x << " = {0.0, 0.0, 0.0};\n";
+      }
+    }
+    leafJ.clear();
+    for (int k : dk) leafJ.insert(producer(dot_ops(d.nodes[k]).first));
+    for (int J : leafJ) {
+      emit(J);
+      os << ind << "qx::sp4<double> w" << J << " = qx::zero4<double>();\n";
+    }
+    // e-_out side trie (dots at its leaves), then e-_in side trie
+    for (int pass = 0; pass < 2; ++pass) {
+      int root_particle = pass == 0 ? pr.i_eout : pr.i_ein;
+      for (int r : blk) {
+        const Node& n = d.nodes[r];
+        if (n.kind != Kind::U || n.particle != root_particle) continue;
+        emit(r);
+        os << ind << "qx::sp4<double> w" << r << " = qx::zero4<double>();\n";
+        for (int c : cons[r]) rev(c, r);
+        if (pass == 0) {
+          std::string m = "m" + std::to_string(pr.i_eout) + "_";
+          os << ind << "{ double g[4]; qx::ubar_vjp(" << m << "0, " << m << "1, " << m << "2, " << m << "3, "
+             << hel_expr(n) << ", 1.0, w" << r << ", g);\n";
+          for (int mu = 0; mu < 4; ++mu) os << ind << "  gm" << pr.i_eout << "_" << mu << " += g[" << mu << "];\n";
+          os << ind << "}\n";
+        }
+      }
+    }
+    // polarisation vectors -> photon momenta
+    for (int x : blk) {
+      const Node& n = d.nodes[x];
+      if (n.kind == Kind::U && n.particle != pr.i_ein && n.particle != pr.i_eout && final_particle(n.particle)) {
+        std::string m = "m" + std::to_string(n.particle) + "_";
+        os << ind << "{ double g[3]; qx::pol_vjp(" << m << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", ge"
+           << x << ", g);\n";
+        for (int mu = 1; mu < 4; ++mu)
+          os << ind << "  gm" << n.particle << "_" << mu << " += g[" << (mu - 1) << "];\n";
+        os << ind << "}\n";
+      }
+    }
+    close_block(outer);
+  }
+
+  // momenta for a partition-local block, opaque to the compiler
+  void block_momenta() {
+    if (mom_src == 0) {
+      os << ind << "long long pq = ptc;\n" << ind << "asm volatile(\"\" : \"+v\"(pq));\n";
+      load_momenta("mom", "N", "pq");
+    } else {
+      for (int p = 0; p < pr.npart; ++p)
+        for (int mu = 0; mu < 4; ++mu)
+          os << ind << "double m" << p << "_" << mu << " = M" << p << "_" << mu << "; asm volatile(\"\" : \"+v\"(m" << p
+             << "_" << mu << "));\n";
     }
   }
 
@@ -345,6 +616,10 @@ void check_variant(const Dag& d, const Variant& v) {
   if (v.mode == HEL_PER_POINT && (v.enum_mask | v.lane_mask | v.loop_mask) != 0)
     throw std::invalid_argument("PER_POINT mode takes every bit from the input");
   if (popc(v.lane_mask) > 6) throw std::invalid_argument("at most 64 lanes per point");
+  if (v.order & 8)
+    for (int a = 0; a < d.proc.P; ++a)
+      if ((v.enum_mask >> d.proc.photon_particle[a]) & 1)
+        throw std::invalid_argument("the partition loop takes photon helicities at run time only");
   if (v.block % 64 != 0 || v.block < 64 || v.block > 1024) throw std::invalid_argument("bad block size");
 }
 
@@ -359,6 +634,11 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   os << "// generated by qedx: " << variant_tag(v, d.proc.n_out, d.proc.n_in) << "\n";
   os << "#include <hip/hip_runtime.h>\n";
   os << device_header_text() << "\n";
+  if (v.order & 8) {
+    e.slot = true;
+    e.slot_tab = kname + "_slots";
+    e.emit_slot_table();
+  }
   os << "extern \"C\" __global__ void __launch_bounds__(" << v.block;
   if (v.min_waves > 0) os << ", " << v.min_waves;
   os << ")\n" << kname
@@ -367,7 +647,7 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   os << "  const long long pt = gid >> " << LB << ";\n";
   os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
   os << "  const long long ptc = pt < N ? pt : N - 1;\n";
-  if (!e.local()) e.load_momenta("mom", "N", "ptc");
+  if (!e.local() && !e.slot) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
   std::string hrt = v.mode == HEL_PER_POINT ? "hel[ptc]" : Emitter::deposit("sub", v.lane_mask);
   e.lane_work(hrt);
@@ -381,13 +661,82 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   return src;
 }
 
+std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* stats) {
+  check_variant(d, v);
+  if (v.loop_mask || v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4))
+    throw std::invalid_argument("gradient kernels take lane and enumerated bits only, SUM, FP64, local blocks");
+  Emitter e(d, v);
+  e.mom_src = 1;
+  const Process& pr = d.proc;
+  const int LB = popc(v.lane_mask), G = 1 << LB;
+  const int NF = pr.n_out + 1;
+  std::ostringstream& os = e.os;
+  os << "extern \"C\" __global__ void __launch_bounds__(" << v.block;
+  if (v.min_waves > 0) os << ", " << v.min_waves;
+  os << ")\n" << kname
+     << "(const double* __restrict__ u, double sqrt_s, long long N, double* __restrict__ logm2, double* __restrict__ "
+        "grad)\n{\n";
+  os << "  const long long gid = (long long)blockIdx.x * " << v.block << " + threadIdx.x;\n";
+  os << "  const long long pt = gid >> " << LB << ";\n";
+  os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
+  os << "  const long long ptc = pt < N ? pt : N - 1;\n";
+  for (int p = 0; p < pr.npart; ++p) os << "  double M" << p << "_0, M" << p << "_1, M" << p << "_2, M" << p << "_3;\n";
+  os << "  {\n    double uu[" << 4 * NF << "];\n";
+  os << "    for (int r = 0; r < " << 4 * NF << "; ++r) uu[r] = u[r * N + ptc];\n";
+  os << "    qx::RamboState<" << NF << "> S;\n    qx::rambo_forward<" << NF << ">(uu, sqrt_s, 1.0, S);\n";
+  os << "    double pin[4], kin[4];\n    qx::incoming_cm(sqrt_s, 1.0, pin, kin);\n";
+  for (int mu = 0; mu < 4; ++mu) os << "    M0_" << mu << " = pin[" << mu << "]; M1_" << mu << " = kin[" << mu << "];\n";
+  for (int j = 0; j < NF; ++j)
+    for (int mu = 0; mu < 4; ++mu) os << "    M" << (2 + j) << "_" << mu << " = S.k[" << j << "][" << mu << "];\n";
+  os << "  }\n";
+  os << "  const unsigned hc = " << Emitter::deposit("sub", v.lane_mask) << ";\n";
+  os << "  double acc = 0.0;\n";
+  e.body();
+  for (int o = 1; o < G; o <<= 1) os << "  acc += __shfl_xor(acc, " << o << ");\n";
+  os << "  const double iM2 = 1.0 / acc;\n";
+  std::vector<int> sums = e.sum_nodes();
+  for (size_t a = 0; a < sums.size(); ++a)
+    os << "  const qx::cx<double> c" << a << " = {A" << a << ".r * iM2, -A" << a << ".i * iM2};\n";
+  for (int p = 2; p < pr.npart; ++p)
+    for (int mu = 0; mu < 4; ++mu) os << "  double gm" << p << "_" << mu << " = 0.0;\n";
+  std::map<uint32_t, std::vector<int>> part;
+  std::vector<uint32_t> order;
+  e.partitions(part, order);
+  for (uint32_t key : order) e.grad_block(key, part[key]);
+  for (int p = 2; p < pr.npart; ++p)
+    for (int mu = 0; mu < 4; ++mu)
+      for (int o = 1; o < G; o <<= 1) os << "  gm" << p << "_" << mu << " += __shfl_xor(gm" << p << "_" << mu << ", " << o << ");\n";
+  os << "  {\n    double uu[" << 4 * NF << "];\n";
+  os << "    for (int r = 0; r < " << 4 * NF << "; ++r) uu[r] = u[r * N + ptc];\n";
+  os << "    qx::RamboState<" << NF << "> S;\n    qx::rambo_forward<" << NF << ">(uu, sqrt_s, 1.0, S);\n";
+  os << "    double gk[" << NF << "][4] = {";
+  for (int j = 0; j < NF; ++j) {
+    os << (j ? ", " : "") << "{";
+    for (int mu = 0; mu < 4; ++mu) os << (mu ? ", " : "") << "gm" << (2 + j) << "_" << mu;
+    os << "}";
+  }
+  os << "};\n";
+  os << "    double gu[" << 4 * NF << "];\n    for (int r = 0; r < " << 4 * NF << "; ++r) gu[r] = 0.0;\n";
+  os << "    qx::rambo_vjp<" << NF << ">(uu, sqrt_s, 1.0, S, gk, gu);\n";
+  os << "    if (pt < N && sub == 0u) {\n      logm2[pt] = log(acc);\n";
+  os << "      for (int r = 0; r < " << 4 * NF << "; ++r) grad[r * N + pt] = gu[r];\n    }\n  }\n}\n";
+  e.st.flops_per_point *= (double)G;
+  if (stats) *stats = e.st;
+  return os.str();
+}
+
 std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* stats) {
   check_variant(d, v);
   Emitter e(d, v);
   std::ostringstream& os = e.os;
+  if (v.order & 8) {
+    e.slot = true;
+    e.slot_tab = fname + "_slots";
+    e.emit_slot_table();
+  }
   os << "static __device__ double " << fname
      << "(const double* __restrict__ mom, long long N, long long ptc, unsigned hrt_in)\n{\n";
-  if (!e.local()) e.load_momenta("mom", "N", "ptc");
+  if (!e.local() && !e.slot) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
   e.lane_work("hrt_in");
   os << "  return acc;\n}\n";

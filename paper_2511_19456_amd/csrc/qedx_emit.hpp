@@ -48,6 +48,14 @@ Dag graph_for(const Process& proc, const Variant& v, double* t_build, double* t_
 // mom: [4*npart][N] SoA (row = 4*particle + mu), out: [N].
 std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* st);
 
+// Gradient kernel (SUM mode, FP64, partition-local blocks, no loop bits):
+//   extern "C" __global__ void <kname>(const double* u, double sqrt_s,
+//                                      long long N, double* logm2, double* grad)
+// RAMBO forward, forward graph (log |M|^2), adjoint graph and adjoint RAMBO
+// in one kernel; u and grad are [4(n+1)][N].  No device header included:
+// the caller prepends it.
+std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* st);
+
 // Device function text of one process body (used by the mixed batch module):
 //   __device__ double <fname>(const double* mom, long long N, long long pt,
 //                             unsigned hrt)

@@ -12,6 +12,12 @@ namespace qedx {
 //   qedx_rambo(const double* u, double sqrt_s, long long N, double* mom)
 // and, for SUM-mode FP64 variants, the gradient kernel
 //   qedx_grad(const double* u, double sqrt_s, long long N, double* logm2, double* grad)
-std::string emit_aux_module(const Process& proc, const Variant& v, int n);
+// grad_lanes / grad_block receive the launch shape of qedx_grad (0 if the
+// module has no gradient kernel).
+std::string emit_aux_module(const Process& proc, const Variant& v, int n, int* grad_lanes, int* grad_block);
+
+// Kernel shape of the gradient: every photon polarisation and as many
+// electron spins as fit on 64 lanes; the rest enumerated in the graph.
+Variant grad_variant(const Process& proc);
 
 }  // namespace qedx

@@ -261,7 +261,8 @@ struct qed_process {
   hipModule_t mod_aux = nullptr;  // RAMBO and gradient kernels
   hipFunction_t f_rambo = nullptr;
   hipFunction_t f_grad = nullptr;
-  int grad_block = 64;
+  int grad_block = 256;
+  int grad_lanes = 0;
   std::string eval_src;
 };
 
@@ -273,10 +274,12 @@ static void default_variant(int n, qed_hel_mode mode, qed_precision prec, Varian
   v.split = P / 2;
   v.block = 256;
   v.join_side = 1;
-  // n <= 3: one shared graph per lane (few partitions, registers suffice);
-  // n >= 4: one basic block per photon partition with its currents
-  // recomputed there, which bounds the live set (measured faster).
-  v.order = n >= 4 ? 4 : 0;
+  // n <= 3: one shared graph per lane (few partitions, registers suffice).
+  // n >= 4: per photon partition, its currents recomputed (bounded live set):
+  // helicity sums use one basic block per partition; per-point kernels a
+  // run-time loop over the partitions around one canonical block (compact
+  // code, seconds to compile even at n = 6).
+  v.order = n >= 4 ? (mode == QED_HEL_PER_POINT ? 8 : 4) : 0;
   if (mode == QED_HEL_SUM) {
     uint32_t all = (1u << (n + 3)) - 1;
     // electron spins over lanes; photon polarisations shared in the graph
@@ -394,7 +397,12 @@ extern "C" qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec,
   s = get_code_object(info.kernel_tag, src, co, meta, hit, ms);
   if (s) return s;
   if (with_aux) {
-    std::string asrc = emit_aux_module(proc, v, n);
+    std::string asrc;
+    try {
+      asrc = emit_aux_module(proc, v, n, nullptr, nullptr);
+    } catch (const std::exception& e) {
+      return fail(QED_ERR_INVALID_ARG, std::string("aux emit: ") + e.what());
+    }
     std::string atag = std::string("aux_") + info.kernel_tag;
     s = get_code_object(atag, asrc, co, meta, hit, ms2);
     if (s) return s;
@@ -431,7 +439,12 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   HIPCHK(hipModuleLoadData(&p->mod, co.data()));
   HIPCHK(hipModuleGetFunction(&p->f_eval, p->mod, "qedx_eval"));
   // auxiliary module: RAMBO (all processes) and the gradient kernel
-  std::string asrc = emit_aux_module(p->proc, p->var, n);
+  std::string asrc;
+  try {
+    asrc = emit_aux_module(p->proc, p->var, n, &p->grad_lanes, &p->grad_block);
+  } catch (const std::exception& e) {
+    return fail(QED_ERR_INVALID_ARG, std::string("aux emit: ") + e.what());
+  }
   std::string aco;
   KernelMeta am;
   bool ahit;
@@ -510,7 +523,7 @@ extern "C" qed_status qed_eval_grad(const qed_process* p, const double* uniforms
   if (!uniforms || !out_logm2 || !out_grad) return fail(QED_ERR_INVALID_ARG, "NULL buffer");
   long long n = (long long)N;
   void* args[] = {(void*)&uniforms, (void*)&sqrt_s, (void*)&n, (void*)&out_logm2, (void*)&out_grad};
-  return launch(p->f_grad, N * (int64_t)p->lanes, p->grad_block, stream, args);
+  return launch(p->f_grad, N * (int64_t)p->grad_lanes, p->grad_block, stream, args);
 }
 
 // ---------------------------------------------------------------------------

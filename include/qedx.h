@@ -140,12 +140,23 @@ typedef struct {
   double* out;           /* device [N] */
 } qed_segment;
 
-/* tile_points = points per work tile (0 = autotuned default).  The plan
- * copies the segment table to the device and instantiates the graph; the
- * segment buffers must stay valid while the plan is launched. */
+/* tile_points = points per work tile, a multiple of 64 (0 = autotuned: a few
+ * grid sizes and tile lengths are timed on the given buffers, which are
+ * overwritten, after a device synchronisation; the choice is cached by plan
+ * signature).  The plan copies the segment table to the device, allocates a
+ * 256-byte tile counter, and instantiates a HIP graph of two kernel nodes
+ * (counter clear, persistent kernel).  The segment buffers must stay valid
+ * while the plan is launched.  Plans are not thread-safe: launches of one plan
+ * on overlapping streams race on its counter. */
 qed_status qed_batch_plan_create(const qed_segment* segs, int nseg, int tile_points, qed_batch_plan** out);
 qed_status qed_batch_launch(qed_batch_plan* plan, void* stream);
 qed_status qed_batch_plan_destroy(qed_batch_plan* plan);
+/* Tile layout chosen for a plan: tiles in the tile space, workgroups of the
+ * persistent grid, 64-point chunks per tile. */
+qed_status qed_batch_info(const qed_batch_plan* plan, int64_t* ntiles, int* grid, int* chunk);
+/* Ahead-of-time build of the batch module for the per-point processes
+ * n_list[0..count) with default kernel shapes (no GPU needed). */
+qed_status qed_batch_prebuild(const int* n_list, int count, qed_precision prec, double* compile_ms);
 
 /* Last error message of the calling thread ("" if none). */
 const char* qed_last_error(void);

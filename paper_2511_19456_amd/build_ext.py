@@ -83,7 +83,7 @@ class QedVariant(ctypes.Structure):
 DEFAULT_KERNELS = [
     (1, 0, 0), (2, 0, 0), (3, 0, 0), (4, 0, 0),
     (1, 1, 0), (2, 1, 0), (3, 1, 0), (4, 1, 0), (5, 1, 0), (6, 1, 0),
-    (3, 0, 1), (4, 1, 1), (5, 1, 1), (6, 1, 1),
+    (3, 0, 1), (1, 1, 1), (2, 1, 1), (3, 1, 1), (4, 1, 1), (5, 1, 1), (6, 1, 1),
 ]
 
 
@@ -114,6 +114,30 @@ def prebuild_kernels(kernels=DEFAULT_KERNELS, jobs: int = 8, verbose: bool = Tru
     return out
 
 
+BATCH_MODULES = [((1, 2, 3, 4, 5, 6), 0), ((1, 2, 3, 4, 5, 6), 1)]
+
+
+def prebuild_batches(verbose: bool = True) -> None:
+    lib = ctypes.CDLL(LIB)
+    lib.qed_batch_prebuild.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_double)]
+    lib.qed_last_error.restype = ctypes.c_char_p
+
+    def one(spec):
+        ns, prec = spec
+        arr = (ctypes.c_int * len(ns))(*ns)
+        ms = ctypes.c_double(0)
+        rc = lib.qed_batch_prebuild(arr, len(ns), prec, ctypes.byref(ms))
+        return spec, rc, ms.value, lib.qed_last_error().decode() if rc else ""
+
+    with cf.ThreadPoolExecutor(max_workers=len(BATCH_MODULES)) as ex:
+        for spec, rc, ms, err in ex.map(one, BATCH_MODULES):
+            if verbose:
+                print(f"[qedx build] batch module {spec}: rc={rc} compile={ms / 1e3:.1f}s", flush=True)
+            if rc:
+                raise RuntimeError(f"batch prebuild failed for {spec}: {err}")
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--no-kernels", action="store_true")
@@ -122,6 +146,7 @@ def main(argv=None) -> None:
     build_library()
     if not a.no_kernels:
         prebuild_kernels(jobs=a.jobs)
+        prebuild_batches()
 
 
 if __name__ == "__main__":

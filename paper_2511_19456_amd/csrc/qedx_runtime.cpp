@@ -29,6 +29,7 @@
 #include "../../include/qedx.h"
 #include "qedx_dag.hpp"
 #include "qedx_emit.hpp"
+#include "qedx_internal.hpp"
 #include "qedx_kernels.hpp"
 
 extern char** environ;
@@ -173,9 +174,6 @@ static int run_hipcc(const std::string& src, const std::string& out, const std::
   return WIFEXITED(status) ? WEXITSTATUS(status) : -4000;
 }
 
-struct KernelMeta {
-  int vgpr = -1, agpr = -1, sgpr = -1, scratch = -1, lds = -1, occupancy = -1;
-};
 
 static KernelMeta parse_meta(const std::string& log) {
   KernelMeta m;
@@ -248,23 +246,6 @@ static qed_status get_code_object(const std::string& tag, const std::string& src
 // ---------------------------------------------------------------------------
 // processes
 // ---------------------------------------------------------------------------
-struct qed_process {
-  int n = 0;
-  qed_hel_mode mode = QED_HEL_SUM;
-  qed_precision prec = QED_FP64;
-  Variant var;
-  Process proc;
-  qed_info info{};
-  int lanes = 1;
-  hipModule_t mod = nullptr;
-  hipFunction_t f_eval = nullptr;
-  hipModule_t mod_aux = nullptr;  // RAMBO and gradient kernels
-  hipFunction_t f_rambo = nullptr;
-  hipFunction_t f_grad = nullptr;
-  int grad_block = 256;
-  int grad_lanes = 0;
-  std::string eval_src;
-};
 
 static void default_variant(int n, qed_hel_mode mode, qed_precision prec, Variant& v) {
   v = Variant();
@@ -608,3 +589,15 @@ extern "C" qed_status qed_graph_metrics(int n, int n_in, uint32_t enum_mask, int
 // ---------------------------------------------------------------------------
 // mixed-process batches (persistent kernel) -- see qedx_batch.cpp
 // ---------------------------------------------------------------------------
+
+namespace qedx_rt {
+qed_status fail(qed_status s, const std::string& msg) { return ::fail(s, msg); }
+qed_status get_code_object(const std::string& tag, const std::string& src, std::string& co, KernelMeta& meta,
+                           bool& hit, double& ms) {
+  return ::get_code_object(tag, src, co, meta, hit, ms);
+}
+std::string cache_dir() { return cache_dir_str(); }
+qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, qedx::Variant& v) {
+  return make_variant(n, mode, prec, nullptr, v);
+}
+}  // namespace qedx_rt

@@ -168,6 +168,11 @@ class BatchPlan:
     def launch(self) -> None:
         check(lib().qed_batch_launch(self._h, _stream()))
 
+    def info(self) -> dict:
+        t, g, c = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        check(lib().qed_batch_info(self._h, ctypes.byref(t), ctypes.byref(g), ctypes.byref(c)))
+        return {"tiles": t.value, "grid": g.value, "chunk": c.value}
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:

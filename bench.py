@@ -1,19 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the batched |M|^2 hot path on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): e- gamma ->
-e- 3 gamma (24 diagrams), FP64, 2^20 phase-space points from RAMBO at
-sqrt(s) = 10 m (seeded uniforms), |M|^2 summed over all 2^6 spin/polarisation
-configurations.  Inputs are generated on the device and resident in HBM before
-the timed region.  One step = one evaluation of the whole batch (qed_eval:
-momentum load, external states, vertices, propagators, joins, diagram sum,
-|A|^2 and helicity sum).
+Headline workload: e- gamma -> e- 3 gamma (24 diagrams), FP64, 2^20
+phase-space points from RAMBO at sqrt(s) = 10 m (seeded uniforms), |M|^2 summed
+over all 2^6 spin/polarisation configurations.  Inputs are generated on the
+device and resident in HBM before the timed region.  One step = one evaluation
+of the whole batch by qed_eval (momentum load, external states, vertices,
+propagators, joins, diagram sum, |A|^2 and helicity sum).
 
 Printed: one JSON line with the throughput, a roofline entry for the eval
 kernel (algorithmic FLOPs = C(DAG) of the node-reduced helicity-summed graph
-per point, against the FP64 vector peak), and the CPU oracle timed on a
-bounded sample on the host cores.  Extra legs (FP32-compensated, mixed batch,
-gradient) are reported under "legs" when those kernels are available.
+per point, against the FP64 vector peak; kernel time from HIP events on the
+launch stream), the CPU oracle timed on a bounded sample on the host cores,
+and further legs on the same GPU: the one-photon workload, the FP32-compensated
+forms (with their error against the FP64 kernel), one random configuration per
+point at n = 5, the mixed n = 1..6 batch in one persistent launch against the
+six plain launches, and the gradient through RAMBO at n = 4.
 """
 import argparse
 import json
@@ -25,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "|M|² phase-space points/s per process (FP64 vs FP32-comp, batched) + % of peak"
-FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # packed FP32
 
 
 def parse():
@@ -35,11 +38,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-legs", action="store_true", help="skip the extra legs")
+    ap.add_argument("--legs", default="", help="comma-separated subset of legs to run")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
 
 def time_launches(fn, steps, warmup):
+    """Average ms per call of fn (which launches on torch's current stream),
+    from HIP events recorded on that stream around `steps` calls."""
     import torch
     for _ in range(warmup):
         fn()
@@ -51,7 +57,7 @@ def time_launches(fn, steps, warmup):
         fn()
     e.record()
     torch.cuda.synchronize()
-    return s.elapsed_time(e) / steps  # ms per launch (kernel-only stream time)
+    return s.elapsed_time(e) / steps
 
 
 def cpu_baseline(u, sqrt_s, n, budget_s):
@@ -71,30 +77,41 @@ def cpu_baseline(u, sqrt_s, n, budget_s):
                       f"{t_used:.1f} s of |M|^2 time"}
 
 
-def traffic_entry(tag):
+def traffic_entry(code_hash):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on this exact code object; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
-            tab = json.load(f)
-        ent = tab.get(tag)
-        if ent:
-            return ent["bytes_per_launch"]
+            ent = json.load(f).get(code_hash)
+        return ent["bytes_per_launch"] if ent else None
     except (OSError, ValueError, KeyError):
-        pass
-    return None
+        return None
+
+
+def alg_flops(n, mode):
+    from paper_2511_19456_amd.qedx import graph_metrics
+    mask = (1 << (n + 3)) - 1 if mode == "sum" else 0
+    return graph_metrics(n, enum_mask=mask, reduced=True)[0]
+
+
+def rel_err_stats(a, b):
+    import torch
+    r = ((a - b).abs() / b.abs()).double()
+    q = torch.quantile(r[: 1 << 20].float(), torch.tensor([0.5, 0.99], device=r.device)).tolist()
+    return {"max": r.max().item(), "p99": q[1], "median": q[0]}
 
 
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); points are independent, "
-              "so sharding is a split of the point range (see DESIGN.md)", file=sys.stderr)
+              "so sharding is a split of the point range (DESIGN.md, 'More than one GPU')", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2511_19456_amd import inputs
-    from paper_2511_19456_amd.qedx import QedProcess, graph_metrics
+    from paper_2511_19456_amd.qedx import QedProcess
 
     dev = torch.device("cuda:0")
     wl = inputs.WORKLOADS["n3_sum_rs10_2p20"]
@@ -110,7 +127,7 @@ def main():
 
     ms = time_launches(lambda: proc.eval(mom, out=out), a.steps, a.warmup)
     value = N / (ms * 1e-3)
-    flops_pt, _ = graph_metrics(n, enum_mask=(1 << (n + 3)) - 1, reduced=True)
+    flops_pt = alg_flops(n, "sum")
     achieved = flops_pt * N / (ms * 1e-3) / 1e12
     rec = {
         "metric": METRIC,
@@ -128,46 +145,149 @@ def main():
         "config": {"workload": "e- gamma -> e- 3gamma, FP64, 2^20 RAMBO points at sqrt(s)=10 m, "
                                "sum over 64 spin/polarisation configurations",
                    "n_photons_out": n, "points": N, "sqrt_s": sqrt_s, "helicity": "sum", "seed": wl["seed"],
-                   "kernel": info["kernel_tag"]},
+                   "kernel": info["kernel_tag"], "code_hash": info["code_hash"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_entry(info["kernel_tag"]),
-                     "flops_per_point": flops_pt, "kernel": "qedx_eval"},
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_entry(info["code_hash"]),
+                     "flops_per_point": flops_pt, "kernel": "qedx_eval",
+                     "executed_flops_per_point": info["flops_per_point"]},
     }
-    legs = {}
+    ref_n3 = out.clone()
     if not a.no_legs:
-        legs.update(extra_legs(torch, np, inputs, QedProcess, dev, a))
-    if legs:
-        rec["legs"] = legs
+        want = set(x for x in a.legs.split(",") if x)
+        rec["legs"] = extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom)
     if not a.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(u, sqrt_s, n, a.cpu_seconds)
     print(json.dumps(rec), flush=True)
 
 
-def extra_legs(torch, np, inputs, QedProcess, dev, a):
-    """FP32-compensated and per-point forms on the same GPU (throughput only)."""
-    legs = {}
-    steps = max(3, a.steps // 4)
+def _leg(legs, key, want, fn):
+    if want and key not in want:
+        return
     try:
-        n, N, rs = 3, 1 << 20, 10.0
-        u, _ = inputs.rambo_inputs(2, n, N)
-        p32 = QedProcess(n, "sum", "fp32c")
-        mom = p32.rambo(torch.as_tensor(u, device=dev), rs)
-        ms = time_launches(lambda: p32.eval(mom), steps, 1)
-        legs["n3_sum_fp32c"] = {"points_per_s": N / (ms * 1e-3), "ms": ms}
-    except Exception as ex:  # a leg that is not built is reported, not fatal
-        legs["n3_sum_fp32c"] = {"error": str(ex)[:200]}
-    for n, rs, prec in ((5, 20.0, "fp64"), (5, 20.0, "fp32c")):
-        key = f"n{n}_per_point_{prec}"
-        try:
-            N = 1 << 20
-            u, h = inputs.rambo_inputs(3, n, N, with_helicities=True)
-            p = QedProcess(n, "per_point", prec)
-            mom = p.rambo(torch.as_tensor(u, device=dev), rs)
-            hel = torch.as_tensor(h.astype(np.int32), device=dev)
-            ms = time_launches(lambda: p.eval(mom, hel), steps, 1)
-            legs[key] = {"points_per_s": N / (ms * 1e-3), "ms": ms}
-        except Exception as ex:
-            legs[key] = {"error": str(ex)[:200]}
+        legs[key] = fn()
+    except Exception as ex:  # a leg that fails is reported in the line, not fatal
+        legs[key] = {"error": f"{type(ex).__name__}: {str(ex)[:300]}"}
+    print(f"[bench] leg {key}: {json.dumps(legs[key])}", file=sys.stderr, flush=True)
+
+
+def extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom_n3):
+    import numpy as np
+    legs = {}
+    steps = max(5, a.steps // 2)
+
+    def rate(ms, N, flops_pt, peak):
+        t = flops_pt * N / (ms * 1e-3) / 1e12
+        return {"ms": ms, "points_per_s": N / (ms * 1e-3), "alg_tflops": t, "frac": t / peak,
+                "flops_per_point": flops_pt}
+
+    def n1_sum():
+        N = 65536
+        m = torch.as_tensor(inputs.compton_lab_momenta(1, N), device=dev)
+        p = QedProcess(1, "sum", "fp64")
+        o = torch.empty(N, dtype=torch.float64, device=dev)
+        ms = time_launches(lambda: p.eval(m, out=o), steps, 2)
+        r = rate(ms, N, alg_flops(1, "sum"), FP64_VECTOR_PEAK_TFLOPS)
+        r["note"] = "65,536 points fill ~1 wave per SIMD: launch/latency bound, roofline fraction not meaningful"
+        return r
+    _leg(legs, "n1_sum_fp64_65536", want, n1_sum)
+
+    def n3_fp32c():
+        N = ref_n3.numel()
+        p = QedProcess(3, "sum", "fp32c")
+        o = torch.empty(N, dtype=torch.float64, device=dev)
+        ms = time_launches(lambda: p.eval(mom_n3, out=o), steps, 2)
+        r = rate(ms, N, alg_flops(3, "sum"), FP32_VECTOR_PEAK_TFLOPS)
+        r["err_vs_fp64_kernel"] = rel_err_stats(o, ref_n3)
+        return r
+    _leg(legs, "n3_sum_fp32c_2p20", want, n3_fp32c)
+
+    wl5 = inputs.WORKLOADS["n5_perpoint_rs20_2p20"]
+    u5, h5 = inputs.rambo_inputs(wl5["seed"], 5, wl5["N"], with_helicities=True)
+    h5d = torch.as_tensor(h5.astype(np.int32), device=dev)
+    p5 = {}
+
+    def n5(prec):
+        def run():
+            p = QedProcess(5, "per_point", prec)
+            p5[prec] = p
+            m = p.rambo(torch.as_tensor(u5, device=dev), wl5["sqrt_s"])
+            o = torch.empty(wl5["N"], dtype=torch.float64, device=dev)
+            ms = time_launches(lambda: p.eval(m, h5d, out=o), steps, 2)
+            r = rate(ms, wl5["N"], alg_flops(5, "per_point"),
+                     FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS)
+            p5[prec + "_out"] = o
+            info = p.info()
+            r.update({"vgpr": info["vgpr"], "agpr": info["agpr"], "scratch": info["scratch_bytes"]})
+            if prec == "fp32c" and "fp64_out" in p5:
+                r["err_vs_fp64_kernel"] = rel_err_stats(o, p5["fp64_out"])
+                r["speedup_vs_fp64"] = legs["n5_per_point_fp64_2p20"]["ms"] / ms
+            return r
+        return run
+    _leg(legs, "n5_per_point_fp64_2p20", want, n5("fp64"))
+    _leg(legs, "n5_per_point_fp32c_2p20", want, n5("fp32c"))
+
+    def mixed(prec):
+        def run():
+            from paper_2511_19456_amd.qedx import BatchPlan
+            spec = inputs.mixed_batch_spec(inputs.WORKLOADS["mixed_n1to6"]["seed"])
+            segs, plain, tot_flops, tot_pts = [], [], 0.0, 0
+            for (n, Np, rs, sub) in spec:
+                u, h = inputs.rambo_inputs(sub, n, Np, with_helicities=True)
+                p = QedProcess(n, "per_point", prec)
+                m = p.rambo(torch.as_tensor(u, device=dev), rs)
+                hd = torch.as_tensor(h.astype(np.int32), device=dev)
+                o = torch.empty(Np, dtype=torch.float64, device=dev)
+                segs.append((p, m, hd, o))
+                tot_flops += alg_flops(n, "per_point") * Np
+                tot_pts += Np
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = BatchPlan(segs, tile_points=0)
+            t_plan = time.perf_counter() - t0
+            ms_b = time_launches(plan.launch, steps, 2)
+            outs_b = [s[3].clone() for s in segs]
+            # the same work as six plain per-process launches (FP64 eval kernels)
+            plain_procs = [(QedProcess(s[0].n, "per_point", "fp64"), s[1], s[2],
+                            torch.empty_like(s[3])) for s in segs]
+
+            def six():
+                for p, m, hd, o in plain_procs:
+                    p.eval(m, hd, out=o)
+            ms_p = time_launches(six, steps, 2)
+            err = max(((ob - pp[3]).abs() / pp[3].abs().clamp_min(1e-300)).max().item()
+                      for ob, pp in zip(outs_b, plain_procs)) if prec == "fp64" else None
+            t = tot_flops / (ms_b * 1e-3) / 1e12
+            peak = FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+            r = {"ms": ms_b, "points_per_s": tot_pts / (ms_b * 1e-3), "alg_tflops": t, "frac": t / peak,
+                 "points": tot_pts, "segments": [(n, Np, round(rs, 3)) for (n, Np, rs, _) in spec],
+                 "plan": plan.info(), "plan_create_s": t_plan, "ms_six_plain_fp64_launches": ms_p,
+                 "speedup_vs_plain_fp64": ms_p / ms_b}
+            if err is not None:
+                r["max_rel_diff_vs_plain"] = err
+            return r
+        return run
+    _leg(legs, "mixed_n1to6_fp64", want, mixed("fp64"))
+    _leg(legs, "mixed_n1to6_fp32c", want, mixed("fp32c"))
+
+    def grad():
+        wl = inputs.WORKLOADS["grad_n4_sum_rs15_2p18"]
+        u, _ = inputs.rambo_inputs(wl["seed"], wl["n"], wl["N"])
+        p = QedProcess(wl["n"], "sum", "fp64")
+        ud = torch.as_tensor(u, device=dev)
+        val = torch.empty(wl["N"], dtype=torch.float64, device=dev)
+        g = torch.empty(4 * (wl["n"] + 1), wl["N"], dtype=torch.float64, device=dev)
+        ms = time_launches(lambda: p.eval_grad(ud, wl["sqrt_s"], out=(val, g)), steps, 2)
+        # forward only (RAMBO + |M|^2) on the same points, for the cost ratio
+        m = torch.empty(4 * (wl["n"] + 3), wl["N"], dtype=torch.float64, device=dev)
+        o = torch.empty(wl["N"], dtype=torch.float64, device=dev)
+
+        def fwd():
+            p.rambo(ud, wl["sqrt_s"], out=m)
+            p.eval(m, out=o)
+        ms_f = time_launches(fwd, steps, 2)
+        return {"ms": ms, "points_per_s": wl["N"] / (ms * 1e-3), "ms_forward_only": ms_f,
+                "grad_over_forward": ms / ms_f}
+    _leg(legs, "grad_n4_sum_fp64_2p18", want, grad)
     return legs
 
 

@@ -78,7 +78,13 @@ typedef struct {
   int32_t split;
   int32_t min_waves;    /* minimum waves per SIMD the compiler must allow (0 = free) */
   int32_t order;        /* emission schedule flags (0 = library default) */
-  int32_t use_defaults; /* nonzero: ignore the fields above */
+  int32_t use_defaults; /* nonzero: ignore the fields above and below */
+  int32_t rewrite;      /* 0 = node reduction only (the paper's CDAG optimisation, App. C);
+                           1 = node reduction followed by the distributive rewrite the paper
+                           proposes (Sec. IV): sums over photon orderings are factored, so the
+                           diagram sum becomes one join per photon partition and the currents
+                           one per photon subset.  Same result up to rounding.  The gradient
+                           kernel always uses the node-reduced graph. */
 } qed_variant;
 
 typedef struct {
@@ -91,7 +97,8 @@ typedef struct {
   int32_t vgpr, agpr, sgpr, scratch_bytes, lds_bytes; /* from the code object */
   double create_ms_build, create_ms_reduce, create_ms_emit, create_ms_compile, create_ms_load;
   int32_t cache_hit;         /* 1 if the code object came from the cache */
-  char kernel_tag[160];
+  char kernel_tag[160];      /* kernel shape: process, mode, precision, helicity coverage, schedule */
+  char code_hash[24];        /* hash of the eval kernel's source, flags and target (changes with the code) */
 } qed_info;
 
 /* Build the graph for n outgoing photons (1..6), reduce it, emit and compile
@@ -168,7 +175,8 @@ const char* qed_cache_dir(void);
  * qed_graph_counts: node counts of the generated graph for n, enumerated
  * helicity bits `enum_mask` and join split `split`: reduced = 0 gives the
  * paper's unreduced form (one chain per diagram, S2 joins); reduced = 1 the
- * node-reduced, join-expanded form.  counts[10] = total, data, compute, U, V,
+ * node-reduced, join-expanded form; reduced = 2 that form after the
+ * distributive rewrite (see qed_variant.rewrite).  counts[10] = total, data, compute, U, V,
  * S1, S2, Dot, Sum, HelSum. */
 qed_status qed_graph_counts(int n, int n_in, uint32_t enum_mask, int split, int reduced, int64_t* counts);
 /* Host interpreter of the graph (float64), per point: value of the exit node

@@ -26,7 +26,7 @@ FP64, FP32C = 0, 1
 class QedVariant(ctypes.Structure):
     _fields_ = [("lane_bits", c_uint32), ("loop_bits", c_uint32), ("block", ctypes.c_int32),
                 ("split", ctypes.c_int32), ("min_waves", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("use_defaults", ctypes.c_int32)]
+                ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32)]
 
 
 class QedInfo(ctypes.Structure):
@@ -39,7 +39,8 @@ class QedInfo(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("create_ms_build", c_double), ("create_ms_reduce", c_double), ("create_ms_emit", c_double),
                 ("create_ms_compile", c_double), ("create_ms_load", c_double),
-                ("cache_hit", ctypes.c_int32), ("kernel_tag", ctypes.c_char * 160)]
+                ("cache_hit", ctypes.c_int32), ("kernel_tag", ctypes.c_char * 160),
+                ("code_hash", ctypes.c_char * 24)]
 
 
 class QedSegment(ctypes.Structure):

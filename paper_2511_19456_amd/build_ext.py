@@ -76,7 +76,7 @@ def build_library(verbose: bool = False) -> None:
 class QedVariant(ctypes.Structure):
     _fields_ = [("lane_bits", ctypes.c_uint32), ("loop_bits", ctypes.c_uint32), ("block", ctypes.c_int32),
                 ("split", ctypes.c_int32), ("min_waves", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("use_defaults", ctypes.c_int32)]
+                ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32)]
 
 
 # (n, mode, precision) built ahead of time: SUM 0 / PER_POINT 1; FP64 0 / FP32C 1

@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <map>
 #include <random>
+#include <set>
+#include <tuple>
 #include <stdexcept>
 #include <unordered_map>
 
@@ -27,6 +29,7 @@ const char* kind_name(Kind k) {
     case Kind::Dot: return "Dot";
     case Kind::Sum: return "Sum";
     case Kind::HelSum: return "HelSum";
+    case Kind::Add: return "Add";
   }
   return "?";
 }
@@ -379,6 +382,163 @@ Dag expand_joins(const Dag& d, int join_side) {
   return r;
 }
 
+// ---------------------------------------------------------------------------
+// Distributive rewrite
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Distributor {
+  const Dag& d;
+  Dag r;
+  std::vector<int32_t> copied;                     // old node -> new node (data nodes and entries)
+  std::map<std::vector<int32_t>, int32_t> sums;    // sorted old terms -> new data node
+
+  explicit Distributor(const Dag& d_) : d(d_), copied(d_.nodes.size(), -1) {
+    r.proc = d.proc;
+    r.enum_mask = d.enum_mask;
+    r.split = d.split;
+    r.expanded = d.expanded;
+    r.join_side = d.join_side;
+    r.distributed = true;
+  }
+
+  // copy an old entry or data node (and what it depends on) unchanged
+  int32_t copy(int32_t i) {
+    if (copied[i] >= 0) return copied[i];
+    const Node& n = d.nodes[i];
+    int32_t id;
+    if (n.kind == Kind::Entry) {
+      Node m = n;
+      m.in.clear();
+      m.out.clear();
+      id = add_node(r, std::move(m));
+    } else if (n.kind == Kind::Data) {
+      const Node& c = d.nodes[n.in[0]];
+      std::vector<int32_t> in;
+      for (int p : c.in) in.push_back(copy(p));
+      Node m = c;
+      m.in = in;
+      m.out.clear();
+      int32_t cid = add_node(r, std::move(m));
+      Node dn = n;
+      dn.in = {cid};
+      dn.out.clear();
+      id = add_node(r, std::move(dn));
+    } else {
+      throw std::logic_error("distribute: copy() takes entry and data nodes");
+    }
+    copied[i] = id;
+    return id;
+  }
+
+  // new data node holding the sum of the old current values `terms`
+  int32_t sum_of(std::vector<int32_t> terms) {
+    std::sort(terms.begin(), terms.end());
+    terms.erase(std::unique(terms.begin(), terms.end()), terms.end());
+    if (terms.size() == 1) return copy(terms[0]);
+    auto it = sums.find(terms);
+    if (it != sums.end()) return it->second;
+    // group the terms by their last linear map: vertex with one photon state,
+    // or propagator of one (side, photon set); anything else stays a term
+    std::map<std::tuple<int, int, int64_t>, std::vector<int32_t>> groups;
+    std::vector<std::tuple<int, int, int64_t>> order;
+    for (int32_t t : terms) {
+      const Node& c = d.nodes[d.nodes[t].in[0]];
+      std::tuple<int, int, int64_t> key;
+      if (c.kind == Kind::V)
+        key = {(int)Kind::V, c.side, (int64_t)c.in[0]};
+      else if (c.kind == Kind::S1)
+        key = {(int)Kind::S1, c.side, (int64_t)c.mask};
+      else
+        key = {(int)c.kind, c.side, -1 - (int64_t)t};
+      if (!groups.count(key)) order.push_back(key);
+      groups[key].push_back(t);
+    }
+    std::vector<int32_t> parts;
+    for (auto& key : order) {
+      const std::vector<int32_t>& g = groups[key];
+      if (g.size() == 1) {
+        parts.push_back(copy(g[0]));
+        continue;
+      }
+      const Node& c0 = d.nodes[d.nodes[g[0]].in[0]];
+      std::vector<int32_t> inner;
+      for (int32_t t : g) {
+        const Node& c = d.nodes[d.nodes[t].in[0]];
+        inner.push_back(c.kind == Kind::V ? c.in[1] : c.in[0]);
+      }
+      int32_t x = sum_of(inner);
+      std::vector<int32_t> in = c0.kind == Kind::V ? std::vector<int32_t>{copy(c0.in[0]), x} : std::vector<int32_t>{x};
+      parts.push_back(add_compute(r, c0.kind, in, c0.side, c0.mask, c0.photon));
+    }
+    const Node& t0 = d.nodes[terms[0]];
+    int32_t id = parts.size() == 1 ? parts[0] : add_compute(r, Kind::Add, parts, t0.side, t0.mask, -1);
+    sums.emplace(terms, id);
+    return id;
+  }
+
+  int32_t side_op(const Node& dot, int side) const {
+    for (int p : dot.in)
+      if (d.nodes[p].side == side) return p;
+    throw std::logic_error("distribute: Dot without an operand of each side");
+  }
+
+  // new data node of a diagram Sum (old data node s)
+  int32_t diagram_sum(int32_t s) {
+    const Node& sc = d.nodes[d.nodes[s].in[0]];
+    // Dots by photon partition (photon set on the e-_in side)
+    std::map<uint32_t, std::vector<int32_t>> part;
+    for (int p : sc.in) {
+      const Node& dot = d.nodes[d.nodes[p].in[0]];
+      if (dot.kind != Kind::Dot) throw std::logic_error("distribute: Sum input is not a Dot");
+      part[d.nodes[side_op(dot, 0)].mask].push_back(p);
+    }
+    std::vector<int32_t> terms;
+    for (auto& kv : part) {
+      std::set<std::pair<int32_t, int32_t>> pairs;
+      std::set<int32_t> Js, Bs;
+      for (int p : kv.second) {
+        const Node& dot = d.nodes[d.nodes[p].in[0]];
+        int32_t J = side_op(dot, 0), B = side_op(dot, 1);
+        pairs.insert({J, B});
+        Js.insert(J);
+        Bs.insert(B);
+      }
+      if (pairs.size() == kv.second.size() && pairs.size() == Js.size() * Bs.size()) {
+        int32_t J = sum_of(std::vector<int32_t>(Js.begin(), Js.end()));
+        int32_t B = sum_of(std::vector<int32_t>(Bs.begin(), Bs.end()));
+        terms.push_back(add_compute(r, Kind::Dot, {J, B}, -1, 0, -1));
+      } else {
+        for (int p : kv.second) terms.push_back(copy(p));  // not a full product: kept as it is
+      }
+    }
+    return add_compute(r, Kind::Sum, terms, -1, 0, -1);
+  }
+
+  void run() {
+    const Node& ex = d.nodes[d.exit];
+    const Node& top = d.nodes[ex.in[0]];
+    if (top.kind == Kind::Sum) {
+      r.exit = diagram_sum(d.exit);
+    } else if (top.kind == Kind::HelSum) {
+      std::vector<int32_t> in;
+      for (int p : top.in) in.push_back(diagram_sum(p));
+      r.exit = add_compute(r, Kind::HelSum, in, -1, 0, -1);
+    } else {
+      throw std::logic_error("distribute: exit is not a Sum or HelSum");
+    }
+  }
+};
+
+}  // namespace
+
+Dag distribute(const Dag& d) {
+  if (!d.expanded) throw std::invalid_argument("distribute() takes a join-expanded graph");
+  Distributor w(d);
+  w.run();
+  return compact(reduce_fixpoint(w.r));
+}
+
 Counts count(const Dag& d) {
   Counts c;
   for (const Node& n : d.nodes) {
@@ -396,6 +556,7 @@ Counts count(const Dag& d) {
       case Kind::Dot: ++c.Dot; break;
       case Kind::Sum: ++c.Sum; break;
       case Kind::HelSum: ++c.HelSum; break;
+      case Kind::Add: ++c.Add; break;
       default: break;
     }
   }
@@ -462,6 +623,7 @@ double node_flops(const Dag& d, int i, bool fp32) {
       return fp32 ? 14.0 * k : 2.0 * (k - 1.0);
     }
     case Kind::HelSum: return 4.0 * (double)n.in.size() - 1.0;
+    case Kind::Add: return 8.0 * ((double)n.in.size() - 1.0);
   }
   return 0.0;
 }
@@ -475,7 +637,8 @@ static double value_bytes(const Dag& d, const Node& n, bool fp32) {
       return ph ? 3 * w : 8 * w;
     }
     case Kind::V:
-    case Kind::S1: return 8 * w;
+    case Kind::S1:
+    case Kind::Add: return 8 * w;
     case Kind::S2:
     case Kind::Dot:
     case Kind::Sum: return 2 * w;
@@ -607,6 +770,11 @@ double interpret(const Dag& d, const double* mom, uint32_t runtime_hel) {
         for (int p : n.in) o.r += v[p].z.r * v[p].z.r + v[p].z.i * v[p].z.i;
         break;
       }
+      case Kind::Add: {
+        o.j = qx::zero4<double>();
+        for (int p : n.in) qx::add_to(o.j, v[p].j);
+        break;
+      }
     }
   }
   const Node& ex = d.nodes[d.exit];
@@ -672,6 +840,10 @@ double interpret_grad(const Dag& d, const double* mom, uint32_t runtime_hel, dou
         o.r = 0.0;
         for (int p : n.in) o.r += v[p].z.r * v[p].z.r + v[p].z.i * v[p].z.i;
         break;
+      case Kind::Add:
+        o.j = qx::zero4<double>();
+        for (int p : n.in) qx::add_to(o.j, v[p].j);
+        break;
     }
   }
   double M2 = 0.0;
@@ -716,6 +888,9 @@ double interpret_grad(const Dag& d, const double* mom, uint32_t runtime_hel, dou
     Adj& w = a[ii];
     switch (n.kind) {
       case Kind::HelSum:
+        break;
+      case Kind::Add:
+        for (int p : n.in) qx::add_to(a[p].w, w.w);
         break;
       case Kind::Sum: {
         qx::cx<double> c = {v[ii].z.r / M2, -v[ii].z.i / M2};

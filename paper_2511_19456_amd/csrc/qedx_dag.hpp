@@ -22,7 +22,8 @@ enum class Kind : uint8_t {
   S2 = 5,     // join: Jbar S(Q) J (paper form, before expansion)
   Dot = 6,    // join after its propagator moved onto one side: Jbar . J
   Sum = 7,    // sum of diagram values of one helicity configuration
-  HelSum = 8  // sum over enumerated helicity configurations of |A|^2
+  HelSum = 8, // sum over enumerated helicity configurations of |A|^2
+  Add = 9     // sum of currents (after the distributive rewrite)
 };
 
 const char* kind_name(Kind k);
@@ -61,11 +62,12 @@ struct Dag {
   int split = 1;            // photons on the e-_in side of every join
   bool expanded = false;    // S2 replaced by S1 + Dot
   int join_side = 1;        // side that carries the join propagator after expansion
+  bool distributed = false; // distributive rewrite applied
 };
 
 struct Counts {
   int64_t total = 0, data = 0, compute = 0;
-  int64_t U = 0, V = 0, S1 = 0, S2 = 0, Dot = 0, Sum = 0, HelSum = 0;
+  int64_t U = 0, V = 0, S1 = 0, S2 = 0, Dot = 0, Sum = 0, HelSum = 0, Add = 0;
 };
 
 // Generator (Sec. II-B, Sec. III-A): one chain per diagram and per enumerated
@@ -86,6 +88,21 @@ int64_t reduce_random_order(Dag& d, uint64_t seed);
 // Rewrite S2(J, Jbar) = Jbar S(Q) J into Dot(J, S1(Jbar)) (join_side = 1) or
 // Dot(S1(J), Jbar) (join_side = 0).  Computationally equivalent (App. B-C).
 Dag expand_joins(const Dag& d, int join_side);
+
+// Distributive rewrite (term rewriting the paper proposes next to node
+// reduction, Sec. IV / App. C), on a reduced, join-expanded graph:
+//  (1) in every diagram Sum, the Dots of one photon partition form the full
+//      product {Jbar_r} x {J_l} of the orderings on each side, so
+//      sum_{r,l} Jbar_r . J_l = (sum_r Jbar_r) . (sum_l J_l);
+//  (2) a sum of currents whose terms share their last linear map (the same
+//      vertex photon state, or the propagator of the same photon set) is
+//      that map applied to the sum of the inner currents, applied
+//      recursively.
+// The diagram sum per configuration goes from (n+1)! Dots to one Dot per
+// partition, and the currents from one per ordered photon prefix to one per
+// photon subset (Berends-Giele recursion).  The result is computationally
+// equivalent (App. B-C) and is node-reduced afterwards.
+Dag distribute(const Dag& d);
 
 Counts count(const Dag& d);
 // Canonical text of a DAG, independent of node numbering.

@@ -284,6 +284,15 @@ template <class T> QEDX_HD void add_to(sp4<T>& w, const sp4<T>& x) {
     w.c[k].i = w.c[k].i + x.c[k].i;
   }
 }
+// sum of two currents (Add node, after the distributive rewrite): 8 FLOPs
+template <class T> QEDX_HD sp4<T> add4(const sp4<T>& a, const sp4<T>& b) {
+  sp4<T> o;
+  for (int k = 0; k < 4; ++k) {
+    o.c[k].r = a.c[k].r + b.c[k].r;
+    o.c[k].i = a.c[k].i + b.c[k].i;
+  }
+  return o;
+}
 template <class T> QEDX_HD sp4<T> zero4() {
   sp4<T> z;
   for (int k = 0; k < 4; ++k) z.c[k] = {T(0), T(0)};

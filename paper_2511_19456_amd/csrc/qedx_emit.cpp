@@ -33,6 +33,7 @@ std::string variant_tag(const Variant& v, int n_out, int n_in) {
   o << "nin" << n_in << "_nout" << n_out << "_p" << v.prec << "_m" << v.mode << "_e" << v.enum_mask << "_l"
     << v.lane_mask << "_o" << v.loop_mask << "_b" << v.block << "_s" << v.split << "_j" << v.join_side << "_r"
     << v.order << "_w" << v.min_waves;
+  if (v.rewrite) o << "_d" << v.rewrite;
   return o.str();
 }
 
@@ -44,6 +45,7 @@ Dag graph_for(const Process& proc, const Variant& v, double* t_build, double* t_
   Dag r = reduce_fixpoint(d);
   r = reduce_fixpoint(expand_joins(r, v.join_side));
   r = compact(r);
+  if (v.rewrite == 1) r = distribute(r);
   auto t2 = clk::now();
   if (t_build) *t_build = std::chrono::duration<double, std::milli>(t1 - t0).count();
   if (t_reduce) *t_reduce = std::chrono::duration<double, std::milli>(t2 - t1).count();
@@ -184,6 +186,14 @@ struct Emitter {
            << ">(" << name(n.in[0]) << ", " << qname(n.side, n.mask) << ");\n";
         st.flops_per_point += 56;
         ++st.n_S1;
+        break;
+      }
+      case Kind::Add: {
+        std::string e = name(n.in[0]);
+        for (size_t t = 1; t < n.in.size(); ++t)
+          e = "qx::add4<" + T + ">(" + e + ", " + name(n.in[t]) + ")";
+        os << ind << "const qx::sp4<" << T << "> " << nm << " = " << e << ";\n";
+        st.flops_per_point += 8.0 * (double)(n.in.size() - 1);
         break;
       }
       case Kind::Dot:
@@ -663,8 +673,9 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
 
 std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* stats) {
   check_variant(d, v);
-  if (v.loop_mask || v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4))
-    throw std::invalid_argument("gradient kernels take lane and enumerated bits only, SUM, FP64, local blocks");
+  if (v.loop_mask || v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4) || d.distributed)
+    throw std::invalid_argument("gradient kernels take lane and enumerated bits only, SUM, FP64, local blocks, "
+                                "the node-reduced graph");
   Emitter e(d, v);
   e.mom_src = 1;
   const Process& pr = d.proc;

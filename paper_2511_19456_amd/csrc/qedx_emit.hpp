@@ -26,6 +26,7 @@ struct Variant {
   int join_side = 1;    // side whose current carries the join propagator
   int order = 0;        // emission order strategy (0 = partition-grouped)
   int min_waves = 0;    // __launch_bounds__ second argument (0 = none)
+  int rewrite = 0;      // 0 = node reduction only; 1 = also the distributive rewrite
 };
 
 struct EmitStats {

@@ -58,6 +58,7 @@ extern "C" qed_status qed_graph_grad_interpret(int n, int split, int reduced, co
   uint32_t all = (1u << pr.npart) - 1;
   Dag d = build_unreduced(pr, all, split);
   if (reduced) d = compact(reduce_fixpoint(expand_joins(reduce_fixpoint(d), 1)));
+  if (reduced == 2) d = distribute(d);
   for (int64_t i = 0; i < N; ++i) val[i] = interpret_grad(d, mom + 4 * pr.npart * i, 0u, gmom + 4 * pr.npart * i);
   return QED_OK;
 }

@@ -12,6 +12,7 @@
 
 struct KernelMeta {
   int vgpr = -1, agpr = -1, sgpr = -1, scratch = -1, lds = -1, occupancy = -1;
+  std::string hash;  // cache key of the code object (hash of source, flags and target)
 };
 
 struct qed_process {
@@ -30,6 +31,10 @@ struct qed_process {
   int grad_block = 256;
   int grad_lanes = 0;
   std::string eval_src;
+  ~qed_process() {
+    if (mod) (void)hipModuleUnload(mod);
+    if (mod_aux) (void)hipModuleUnload(mod_aux);
+  }
 };
 
 namespace qedx_rt {

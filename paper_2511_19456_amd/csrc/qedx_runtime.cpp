@@ -210,6 +210,7 @@ static qed_status get_code_object(const std::string& tag, const std::string& src
       std::string lg;
       read_file(log, lg);
       meta = parse_meta(lg);
+      meta.hash = h;
       hit = true;
       return QED_OK;
     }
@@ -240,6 +241,7 @@ static qed_status get_code_object(const std::string& tag, const std::string& src
   rename(tmpo.c_str(), path.c_str());
   write_file(sum, hex64(fnv1a(co.data(), co.size())));
   meta = parse_meta(lg);
+  meta.hash = h;
   return QED_OK;
 }
 
@@ -291,6 +293,8 @@ static qed_status make_variant(int n, qed_hel_mode mode, qed_precision prec, con
     if (qv->split) v.split = qv->split;
     v.min_waves = qv->min_waves;
     if (qv->order) v.order = qv->order;
+    if (qv->rewrite < 0 || qv->rewrite > 1) return fail(QED_ERR_INVALID_ARG, "rewrite must be 0 or 1");
+    v.rewrite = qv->rewrite;
     if (mode == QED_HEL_SUM) {
       uint32_t all = (1u << (n + 3)) - 1;
       v.lane_mask = qv->lane_bits & all;
@@ -416,6 +420,7 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   p->info.sgpr = meta.sgpr;
   p->info.scratch_bytes = meta.scratch;
   p->info.lds_bytes = meta.lds;
+  snprintf(p->info.code_hash, sizeof p->info.code_hash, "%s", meta.hash.c_str());
   auto t0 = std::chrono::steady_clock::now();
   HIPCHK(hipModuleLoadData(&p->mod, co.data()));
   HIPCHK(hipModuleGetFunction(&p->f_eval, p->mod, "qedx_eval"));
@@ -443,10 +448,7 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
 }
 
 extern "C" qed_status qed_process_destroy(qed_process* p) {
-  if (!p) return QED_OK;
-  if (p->mod) (void)hipModuleUnload(p->mod);
-  if (p->mod_aux) (void)hipModuleUnload(p->mod_aux);
-  delete p;
+  delete p;  // unloads its modules
   return QED_OK;
 }
 
@@ -517,6 +519,7 @@ static Dag tool_graph(int n, int n_in, uint32_t enum_mask, int split, int reduce
     d = reduce_fixpoint(d);
     d = compact(reduce_fixpoint(expand_joins(d, 1)));
   }
+  if (reduced == 2) d = distribute(d);
   return d;
 }
 

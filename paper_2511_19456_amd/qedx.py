@@ -45,8 +45,10 @@ def _dev_tensor(t: torch.Tensor, dtype: torch.dtype, rows: int, name: str) -> to
 
 
 def make_variant(lane_bits: int = 0, loop_bits: int = 0, block: int = 0, split: int = 0,
-                 min_waves: int = 0, order: int = 0) -> QedVariant:
-    return QedVariant(lane_bits, loop_bits, block, split, min_waves, order, 0)
+                 min_waves: int = 0, order: int = 0, rewrite: int = 0) -> QedVariant:
+    """Kernel shape (fields of qed_variant); rewrite=1 adds the distributive
+    rewrite after node reduction.  Zero fields take the library default."""
+    return QedVariant(lane_bits, loop_bits, block, split, min_waves, order, 0, rewrite)
 
 
 class QedProcess:
@@ -89,6 +91,7 @@ class QedProcess:
         check(lib().qed_process_info(self._h, ctypes.byref(inf)))
         d = {k: getattr(inf, k) for k, _ in QedInfo._fields_}
         d["kernel_tag"] = inf.kernel_tag.decode()
+        d["code_hash"] = inf.code_hash.decode()
         return d
 
     def eval(self, momenta: torch.Tensor, hel: Optional[torch.Tensor] = None,
@@ -116,12 +119,20 @@ class QedProcess:
         check(lib().qed_rambo(self._h, _ptr(uniforms), float(sqrt_s), N, _ptr(out), _stream()))
         return out
 
-    def eval_grad(self, uniforms: torch.Tensor, sqrt_s: float):
-        """(log|M|^2 [N], d log|M|^2 / d uniforms [4(n+1), N]) through RAMBO."""
+    def eval_grad(self, uniforms: torch.Tensor, sqrt_s: float, out: Optional[tuple] = None):
+        """(log|M|^2 [N], d log|M|^2 / d uniforms [4(n+1), N]) through RAMBO.
+        `out` = (val, grad) preallocated device tensors, or None."""
         _dev_tensor(uniforms, torch.float64, 4 * (self.n + 1), "uniforms")
         N = uniforms.shape[1]
-        val = torch.empty(N, dtype=torch.float64, device=uniforms.device)
-        grad = torch.empty(4 * (self.n + 1), N, dtype=torch.float64, device=uniforms.device)
+        if out is None:
+            val = torch.empty(N, dtype=torch.float64, device=uniforms.device)
+            grad = torch.empty(4 * (self.n + 1), N, dtype=torch.float64, device=uniforms.device)
+        else:
+            val, grad = out
+            _dev_tensor(grad, torch.float64, 4 * (self.n + 1), "grad")
+            if val.shape != (N,) or val.dtype != torch.float64 or not val.is_cuda or not val.is_contiguous() \
+                    or grad.shape[1] != N:
+                raise ValueError("out must be (float64 [N], float64 [4(n+1), N]) contiguous device tensors")
         check(lib().qed_eval_grad(self._h, _ptr(uniforms), float(sqrt_s), None, N, _ptr(val), _ptr(grad),
                                   _stream()))
         return val, grad

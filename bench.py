@@ -40,7 +40,23 @@ def parse():
     ap.add_argument("--no-legs", action="store_true", help="skip the extra legs")
     ap.add_argument("--legs", default="", help="comma-separated subset of legs to run")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 512 MiB three times (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of known size: 512 MiB read and 512 MiB written per launch.
+    rocprofv3's FETCH_SIZE / WRITE_SIZE on this kernel give the factor that
+    turns those counters into bytes."""
+    import torch
+    n = 1 << 26
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": 8 * n, "copy_bytes_written_per_launch": 8 * n}), flush=True)
 
 
 def time_launches(fn, steps, warmup):
@@ -104,6 +120,9 @@ def rel_err_stats(a, b):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration()
+        return
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); points are independent, "
               "so sharding is a split of the point range (DESIGN.md, 'More than one GPU')", file=sys.stderr)

@@ -64,10 +64,11 @@ typedef enum { QED_HEL_SUM = 0, QED_HEL_PER_POINT = 1 } qed_hel_mode;
  * workloads (measured, not guaranteed for arbitrary points). */
 typedef enum { QED_FP64 = 0, QED_FP32C = 1 } qed_precision;
 
-/* Kernel shape knobs (all zero = library default for the process).
- * lane_bits:  helicity bits spread over lanes (2^lane_bits lanes per point),
+/* Kernel shape knobs (a zero field = library default for the process).
+ * lane_bits:  helicity bits spread over lanes (2^popcount lanes per point),
  *             given as a mask over particle bits; SUM mode only.
  * loop_bits:  helicity bits enumerated by a run-time loop; SUM mode only.
+ *             lane_bits = loop_bits = 0 keeps the default coverage.
  * The remaining bits are enumerated inside the graph.  block = threads per
  * workgroup (multiple of 64, <= 1024).  split = photons on the e-_in side
  * of every join (1..n). */

@@ -295,12 +295,13 @@ static qed_status make_variant(int n, qed_hel_mode mode, qed_precision prec, con
     if (qv->order) v.order = qv->order;
     if (qv->rewrite < 0 || qv->rewrite > 1) return fail(QED_ERR_INVALID_ARG, "rewrite must be 0 or 1");
     v.rewrite = qv->rewrite;
-    if (mode == QED_HEL_SUM) {
+    if (mode == QED_HEL_SUM && (qv->lane_bits || qv->loop_bits)) {
+      // both zero keeps the default helicity coverage
       uint32_t all = (1u << (n + 3)) - 1;
       v.lane_mask = qv->lane_bits & all;
       v.loop_mask = qv->loop_bits & all & ~v.lane_mask;
       v.enum_mask = all & ~v.lane_mask & ~v.loop_mask;
-    } else if (qv->lane_bits || qv->loop_bits) {
+    } else if (mode != QED_HEL_SUM && (qv->lane_bits || qv->loop_bits)) {
       return fail(QED_ERR_INVALID_ARG, "lane_bits/loop_bits apply to SUM mode only");
     }
   }

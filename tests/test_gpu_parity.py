@@ -166,11 +166,13 @@ def test_gradient_vs_oracle(n, sqrt_s, N):
 
 
 def test_gradient_vs_central_differences_and_autograd():
-    """Central differences with h = 1e-6 on the uniforms.  A point is judged
-    where the difference quotient itself is reliable: its truncation error,
-    estimated from h and h/2 (Richardson), below 1e-7 of the gradient norm, and
-    every uniform at least 1e-5 from the ends of (0,1).  At least 98 % of the
-    points must qualify, and the adjoint must agree there to 1e-6 normwise."""
+    """Central differences with h = 1e-6 on the uniforms, at points whose
+    uniforms all lie at least 1e-5 from the ends of (0,1).  The difference
+    quotient has its own truncation error (h^2/6 times the third derivative,
+    large where the kinematics approach a soft or collinear photon); it is
+    estimated per point from the quotients at h and h/2 (Richardson:
+    4/3 |D(h) - D(h/2)|) and added to the 1e-6 normwise tolerance.  Most points
+    must also agree to 1e-6 with no allowance at all."""
     from paper_2511_19456_amd.qedx import QedLogM2
     n, sqrt_s, N = 4, 15.0, 1024
     u, _ = inputs.rambo_inputs(5, n, N)
@@ -190,11 +192,15 @@ def test_gradient_vs_central_differences_and_autograd():
     fd1, fd2 = fdiff(1e-6), fdiff(5e-7)
     gn = torch.linalg.norm(g, dim=0)
     trunc = (torch.linalg.norm(fd1 - fd2, dim=0) * 4.0 / 3.0 / gn).cpu().numpy()
-    keep = np.all((u > 1e-5) & (u < 1 - 1e-5), axis=0) & (trunc < 1e-7)
+    keep = np.all((u > 1e-5) & (u < 1 - 1e-5), axis=0)
     err = (torch.linalg.norm(g - fd1, dim=0) / gn).cpu().numpy()
-    print(f"FD check: {keep.sum()} of {N} points judged; max err {err[keep].max():.2e}, median {np.median(err):.2e}")
-    assert keep.mean() > 0.98
-    assert err[keep].max() < 1e-6
+    plain = err[keep] < 1e-6
+    print(f"FD check: {keep.sum()} of {N} points away from the ends; {plain.sum()} within 1e-6 outright; "
+          f"max err {err[keep].max():.2e}, median {np.median(err[keep]):.2e}, max FD error estimate "
+          f"{trunc[keep].max():.2e}")
+    assert keep.mean() > 0.95
+    assert np.all(err[keep] < 1e-6 + 2.0 * trunc[keep])
+    assert plain.mean() > 0.95 and np.median(err[keep]) < 1e-8
     # torch.autograd.Function wrapper
     x = ud.clone().requires_grad_(True)
     y = QedLogM2.apply(x, p, sqrt_s)
@@ -267,3 +273,49 @@ def test_mixed_batch_matches_per_process_and_oracle(prec, tile):
             tot = O.m2(ref_mom, n, "sum").numpy() if n < 5 else np.abs(ref)
             scale = tot / (1 << (n + 3)) if n < 5 else np.abs(ref)
             assert _per_point_err(out.cpu().numpy()[idx], ref, scale).max() < 1e-10, n
+
+
+# ---------------------------------------------------------------------------
+# distributive rewrite (rewrite = 1): same |M|^2 as the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,mode,sqrt_s,lanes,N", [(2, "sum", 6.0, 0, 333), (3, "sum", 10.0, 0, 517),
+                                                   (3, "sum", 10.0, 7, 517), (4, "sum", 15.0, 0, 160),
+                                                   (4, "per_point", 15.0, 0, 300), (5, "per_point", 20.0, 0, 200),
+                                                   (6, "per_point", 25.0, 0, 40)])
+def test_distributive_rewrite_fp64(n, mode, sqrt_s, lanes, N):
+    from paper_2511_19456_amd.qedx import make_variant
+    u, hel = inputs.rambo_inputs(31, n, N, with_helicities=True)
+    ref_mom = O.momenta_soa_from_uniforms(u, sqrt_s, n)
+    p = _proc(n, mode, "fp64", make_variant(lane_bits=lanes, rewrite=1))
+    assert p.info()["kernel_tag"].endswith("_d1")
+    h = torch.as_tensor(hel.astype(np.int32), device=DEV) if mode == "per_point" else None
+    got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV), h).cpu().numpy()
+    ref = O.m2(ref_mom, n, mode, hel).numpy()
+    if mode == "sum":
+        err = _rel(got, ref)
+    else:
+        # per-configuration values: relative to the point's value, floored at
+        # 1e-3 of the segment's median (values can vanish where diagrams cancel)
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.median(np.abs(ref)))
+    assert err.max() < 1e-10
+
+
+@pytest.mark.parametrize("n,mode,sqrt_s", [(3, "sum", 10.0), (5, "per_point", 20.0)])
+def test_distributive_rewrite_fp32c(n, mode, sqrt_s):
+    from paper_2511_19456_amd.qedx import make_variant
+    N = 4096
+    u, hel = inputs.rambo_inputs(3, n, N, with_helicities=True)
+    ref_mom = O.momenta_soa_from_uniforms(u, sqrt_s, n)
+    p = _proc(n, mode, "fp32c", make_variant(rewrite=1))
+    h = torch.as_tensor(hel.astype(np.int32), device=DEV) if mode == "per_point" else None
+    got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV), h).cpu().numpy()
+    ref = O.m2(ref_mom, n, mode, hel).numpy()
+    if mode == "sum":
+        err = _rel(got, ref)
+    else:
+        scale = O.m2(ref_mom, n, "sum").numpy() / (1 << (n + 3))
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
+    print(f"fp32c rewrite n={n} {mode}: max {err.max():.2e} p99 {np.quantile(err, 0.99):.2e} "
+          f"median {np.median(err):.2e}")
+    assert err.max() < 1e-4
+    assert np.median(err) < 1e-5

@@ -284,6 +284,22 @@ template <class T> QEDX_HD void add_to(sp4<T>& w, const sp4<T>& x) {
     w.c[k].i = w.c[k].i + x.c[k].i;
   }
 }
+// A current in per-lane LDS slots: component k at p[k * stride] (stride =
+// threads per block, so a wavefront's accesses are consecutive words).
+template <class T> QEDX_HD void lds_put(T* p, int stride, const sp4<T>& x) {
+  for (int k = 0; k < 4; ++k) {
+    p[(2 * k) * stride] = x.c[k].r;
+    p[(2 * k + 1) * stride] = x.c[k].i;
+  }
+}
+template <class T> QEDX_HD sp4<T> lds_get(const T* p, int stride) {
+  sp4<T> x;
+  for (int k = 0; k < 4; ++k) {
+    x.c[k].r = p[(2 * k) * stride];
+    x.c[k].i = p[(2 * k + 1) * stride];
+  }
+  return x;
+}
 // sum of two currents (Add node, after the distributive rewrite): 8 FLOPs
 template <class T> QEDX_HD sp4<T> add4(const sp4<T>& a, const sp4<T>& b) {
   sp4<T> o;

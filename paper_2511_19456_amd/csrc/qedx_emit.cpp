@@ -87,7 +87,19 @@ struct Emitter {
     const Node& n = d.nodes[i];
     return n.kind == Kind::Data ? n.in[0] : i;
   }
-  std::string name(int i) const { return "n" + std::to_string(producer(i)); }
+  std::string name(int i) const {
+    auto a = alias.find(producer(i));
+    return a != alias.end() ? a->second : "n" + std::to_string(producer(i));
+  }
+  // LDS staging of the held side of each partition block (order flag 16):
+  // the held currents are stored to per-lane LDS slots once and read back,
+  // through an address the compiler cannot see through, for every group of
+  // kTile streamed currents -- register pressure is then the accumulators,
+  // one tile and one held current.
+  std::map<int, std::string> alias;
+  bool stage() const { return (v.order & 16) != 0; }
+  int lds_slots = 0;
+  static constexpr int kTile = 4;
 
   void emitK(uint32_t mask) {
     if (kdone.count(mask)) return;
@@ -297,6 +309,52 @@ struct Emitter {
     if (local()) close_block(outer);
   }
 
+  // opaque per-use LDS index (the base stays visible, so accesses stay ds_*)
+  std::string lds_index(int slot) const {
+    return "int ix = " + std::to_string(slot * 8 * v.block) + " + (int)threadIdx.x; asm volatile(\"\" : \"+v\"(ix));";
+  }
+
+  void staged_block(const std::vector<int>& dk, const std::set<int>& hold, const std::set<int>& stream, bool holdB) {
+    std::vector<int> hv(hold.begin(), hold.end()), sv(stream.begin(), stream.end());
+    lds_slots = std::max(lds_slots, (int)hv.size());
+    for (size_t k = 0; k < hv.size(); ++k) {
+      emit(hv[k]);
+      os << ind << "{ " << lds_index((int)k) << " qx::lds_put<" << T << ">(qx_lds + ix, " << v.block << ", "
+         << name(hv[k]) << "); }\n";
+    }
+    std::map<std::pair<int, int>, std::vector<int>> dots;  // (held, streamed) -> Dot nodes
+    for (int k : dk) {
+      auto ops = dot_ops(d.nodes[k]);
+      int J = producer(ops.first), B = producer(ops.second);
+      dots[holdB ? std::make_pair(B, J) : std::make_pair(J, B)].push_back(k);
+    }
+    for (size_t t0 = 0; t0 < sv.size(); t0 += kTile) {
+      size_t t1 = std::min(sv.size(), t0 + kTile);
+      for (size_t t = t0; t < t1; ++t) emit(sv[t]);
+      for (size_t k = 0; k < hv.size(); ++k) {
+        bool any = false;
+        for (size_t t = t0; t < t1 && !any; ++t) any = dots.count({hv[k], sv[t]}) > 0;
+        if (!any) continue;
+        std::string tmp = "h" + std::to_string(hv[k]) + "_" + std::to_string(t0);
+        os << ind << "{\n";
+        std::string outer = ind;
+        ind += "  ";
+        os << ind << lds_index((int)k) << "\n";
+        os << ind << "const qx::sp4<" << T << "> " << tmp << " = qx::lds_get<" << T << ">(qx_lds + ix, " << v.block
+           << ");\n";
+        alias[hv[k]] = tmp;
+        for (size_t t = t0; t < t1; ++t) {
+          auto it = dots.find({hv[k], sv[t]});
+          if (it == dots.end()) continue;
+          for (int dkk : it->second) emit_dot(dkk);
+        }
+        alias.erase(hv[k]);
+        ind = outer;
+        os << ind << "}\n";
+      }
+    }
+  }
+
   void forward_block_inner(uint32_t key, const std::vector<int>& dk) {
     (void)key;
     std::set<int> Bs, Js;
@@ -308,6 +366,10 @@ struct Emitter {
     bool holdB = Bs.size() <= Js.size();
     const std::set<int>& hold = holdB ? Bs : Js;
     const std::set<int>& stream = holdB ? Js : Bs;
+    if (stage()) {
+      staged_block(dk, hold, stream, holdB);
+      return;
+    }
     for (int h : hold) emit(h);
     for (int s : stream) {
       emit(s);
@@ -653,6 +715,8 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   if (v.min_waves > 0) os << ", " << v.min_waves;
   os << ")\n" << kname
      << "(const double* __restrict__ mom, const unsigned* __restrict__ hel, long long N, double* __restrict__ out)\n{\n";
+  const std::string lds_mark = "  //@LDS@\n";
+  os << lds_mark;
   os << "  const long long gid = (long long)blockIdx.x * " << v.block << " + threadIdx.x;\n";
   os << "  const long long pt = gid >> " << LB << ";\n";
   os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
@@ -666,6 +730,14 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   // per point: every lane of the group does the body once per loop iteration
   e.st.flops_per_point *= (double)G * (double)(1 << popc(v.loop_mask));
   std::string src = os.str();
+  {
+    // per-lane LDS slots for staged currents: [slot][8 words][block]
+    std::string decl;
+    if (e.lds_slots > 0)
+      decl = "  __shared__ " + e.T + " qx_lds[" + std::to_string(e.lds_slots * 8 * v.block) + "];\n";
+    size_t at = src.find(lds_mark);
+    src.replace(at, lds_mark.size(), decl);
+  }
   e.st.lines = std::count(src.begin(), src.end(), '\n');
   if (stats) *stats = e.st;
   return src;
@@ -673,9 +745,8 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
 
 std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* stats) {
   check_variant(d, v);
-  if (v.loop_mask || v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4) || d.distributed)
-    throw std::invalid_argument("gradient kernels take lane and enumerated bits only, SUM, FP64, local blocks, "
-                                "the node-reduced graph");
+  if (v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4) || (v.order & 16) || d.distributed)
+    throw std::invalid_argument("gradient kernels take SUM, FP64, local blocks, the node-reduced graph");
   Emitter e(d, v);
   e.mom_src = 1;
   const Process& pr = d.proc;
@@ -700,20 +771,58 @@ std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& 
   for (int j = 0; j < NF; ++j)
     for (int mu = 0; mu < 4; ++mu) os << "    M" << (2 + j) << "_" << mu << " = S.k[" << j << "][" << mu << "];\n";
   os << "  }\n";
-  os << "  const unsigned hc = " << Emitter::deposit("sub", v.lane_mask) << ";\n";
+  // Helicity bits: lane bits from the lane index, enumerated bits inside the
+  // graph, loop bits by a run-time loop.  With loop bits the forward graph
+  // runs twice: once over all iterations for |M|^2, then again per iteration
+  // for the amplitudes that seed that iteration's adjoint sweep (recomputed,
+  // not stored).
+  const int nloop = popc(v.loop_mask);
+  os << "  const unsigned hrt = " << Emitter::deposit("sub", v.lane_mask) << ";\n";
   os << "  double acc = 0.0;\n";
-  e.body();
-  for (int o = 1; o < G; o <<= 1) os << "  acc += __shfl_xor(acc, " << o << ");\n";
-  os << "  const double iM2 = 1.0 / acc;\n";
-  std::vector<int> sums = e.sum_nodes();
-  for (size_t a = 0; a < sums.size(); ++a)
-    os << "  const qx::cx<double> c" << a << " = {A" << a << ".r * iM2, -A" << a << ".i * iM2};\n";
-  for (int p = 2; p < pr.npart; ++p)
-    for (int mu = 0; mu < 4; ++mu) os << "  double gm" << p << "_" << mu << " = 0.0;\n";
   std::map<uint32_t, std::vector<int>> part;
   std::vector<uint32_t> order;
   e.partitions(part, order);
-  for (uint32_t key : order) e.grad_block(key, part[key]);
+  std::vector<int> sums = e.sum_nodes();
+  auto seeds_and_adjoint = [&]() {
+    for (size_t a = 0; a < sums.size(); ++a)
+      os << e.ind << "const qx::cx<double> c" << a << " = {A" << a << ".r * iM2, -A" << a << ".i * iM2};\n";
+    for (uint32_t key : order) e.grad_block(key, part[key]);
+  };
+  auto gm_init = [&]() {
+    for (int p = 2; p < pr.npart; ++p)
+      for (int mu = 0; mu < 4; ++mu) os << "  double gm" << p << "_" << mu << " = 0.0;\n";
+  };
+  auto reduce_acc = [&]() {
+    for (int o = 1; o < G; o <<= 1) os << "  acc += __shfl_xor(acc, " << o << ");\n";
+    os << "  const double iM2 = 1.0 / acc;\n";
+  };
+  if (nloop == 0) {
+    os << "  const unsigned hc = hrt;\n";
+    e.body();
+    reduce_acc();
+    gm_init();
+    seeds_and_adjoint();
+  } else {
+    const std::string loop_head = "  #pragma unroll 1\n  for (unsigned lp = 0; lp < " + std::to_string(1u << nloop) +
+                                  "u; ++lp) {\n    const unsigned hc = hrt | " + Emitter::deposit("lp", v.loop_mask) +
+                                  ";\n";
+    const std::string ind0 = e.ind;
+    os << loop_head;
+    e.ind = "    ";
+    e.body();
+    e.ind = ind0;
+    os << "  }\n";
+    reduce_acc();
+    gm_init();
+    os << loop_head;
+    e.ind = "    ";
+    os << e.ind << "double acc = 0.0;\n";  // |A|^2 of the recomputed pass, unused
+    e.body();
+    os << e.ind << "(void)acc;\n";
+    seeds_and_adjoint();
+    e.ind = ind0;
+    os << "  }\n";
+  }
   for (int p = 2; p < pr.npart; ++p)
     for (int mu = 0; mu < 4; ++mu)
       for (int o = 1; o < G; o <<= 1) os << "  gm" << p << "_" << mu << " += __shfl_xor(gm" << p << "_" << mu << ", " << o << ");\n";
@@ -731,13 +840,14 @@ std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& 
   os << "    qx::rambo_vjp<" << NF << ">(uu, sqrt_s, 1.0, S, gk, gu);\n";
   os << "    if (pt < N && sub == 0u) {\n      logm2[pt] = log(acc);\n";
   os << "      for (int r = 0; r < " << 4 * NF << "; ++r) grad[r * N + pt] = gu[r];\n    }\n  }\n}\n";
-  e.st.flops_per_point *= (double)G;
+  e.st.flops_per_point *= (double)G * (double)(1 << popc(v.loop_mask));
   if (stats) *stats = e.st;
   return os.str();
 }
 
 std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* stats) {
   check_variant(d, v);
+  if (v.order & 16) throw std::invalid_argument("LDS staging is built for eval kernels only");
   Emitter e(d, v);
   std::ostringstream& os = e.os;
   if (v.order & 8) {

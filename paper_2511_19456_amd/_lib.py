@@ -40,7 +40,7 @@ class QedInfo(ctypes.Structure):
                 ("create_ms_build", c_double), ("create_ms_reduce", c_double), ("create_ms_emit", c_double),
                 ("create_ms_compile", c_double), ("create_ms_load", c_double),
                 ("cache_hit", ctypes.c_int32), ("kernel_tag", ctypes.c_char * 160),
-                ("code_hash", ctypes.c_char * 24)]
+                ("code_hash", ctypes.c_char * 24), ("kernel_name", ctypes.c_char * 48)]
 
 
 class QedSegment(ctypes.Structure):

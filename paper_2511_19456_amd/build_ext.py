@@ -79,11 +79,20 @@ class QedVariant(ctypes.Structure):
                 ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32)]
 
 
-# (n, mode, precision) built ahead of time: SUM 0 / PER_POINT 1; FP64 0 / FP32C 1
+# (n, mode, precision[, variant fields]) built ahead of time: SUM 0 / PER_POINT 1;
+# FP64 0 / FP32C 1.  The variant fields are keyword arguments of QedVariant
+# (lane_bits, order, rewrite, ...); absent = the library default shape.
 DEFAULT_KERNELS = [
     (1, 0, 0), (2, 0, 0), (3, 0, 0), (4, 0, 0),
     (1, 1, 0), (2, 1, 0), (3, 1, 0), (4, 1, 0), (5, 1, 0), (6, 1, 0),
     (3, 0, 1), (1, 1, 1), (2, 1, 1), (3, 1, 1), (4, 1, 1), (5, 1, 1), (6, 1, 1),
+    # distributive rewrite (bench legs and parity tests)
+    (2, 0, 0, dict(rewrite=1)), (3, 0, 0, dict(rewrite=1)), (3, 0, 0, dict(rewrite=1, lane_bits=7)),
+    (4, 0, 0, dict(rewrite=1)), (4, 1, 0, dict(rewrite=1)), (5, 1, 0, dict(rewrite=1)), (6, 1, 0, dict(rewrite=1)),
+    (3, 0, 1, dict(rewrite=1)), (5, 1, 1, dict(rewrite=1)),
+    # kernel shapes the parity tests exercise
+    (3, 0, 0, dict(lane_bits=7)), (3, 0, 0, dict(lane_bits=5, order=4)), (3, 0, 0, dict(lane_bits=63, order=4)),
+    (3, 1, 0, dict(order=4)),
 ]
 
 
@@ -95,20 +104,24 @@ def prebuild_kernels(kernels=DEFAULT_KERNELS, jobs: int = 8, verbose: bool = Tru
     lib.qed_last_error.restype = ctypes.c_char_p
 
     def one(k):
-        n, mode, prec = k
+        n, mode, prec = k[:3]
+        var = None
+        if len(k) > 3:
+            var = QedVariant(**k[3])
         ms = ctypes.c_double(0.0)
         t = time.time()
-        rc = lib.qed_prebuild(n, mode, prec, None, 1, ctypes.byref(ms))
+        rc = lib.qed_prebuild(n, mode, prec, ctypes.byref(var) if var is not None else None, 1, ctypes.byref(ms))
         err = lib.qed_last_error().decode() if rc else ""
         return k, rc, ms.value, time.time() - t, err
 
     out = {}
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for k, rc, ms, wall, err in ex.map(one, kernels):
-            out[k] = (rc, ms)
+            out[str(k)] = (rc, ms)
             if verbose:
-                print(f"[qedx build] kernel n={k[0]} mode={k[1]} prec={k[2]}: rc={rc} compile={ms / 1e3:.1f}s",
-                      flush=True)
+                extra = f" {k[3]}" if len(k) > 3 else ""
+                print(f"[qedx build] kernel n={k[0]} mode={k[1]} prec={k[2]}{extra}: rc={rc} "
+                      f"compile={ms / 1e3:.1f}s", flush=True)
             if rc:
                 raise RuntimeError(f"kernel prebuild failed for {k}: {err}")
     return out

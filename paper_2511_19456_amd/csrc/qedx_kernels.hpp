@@ -9,10 +9,10 @@
 namespace qedx {
 
 // HIP source with
-//   qedx_rambo(const double* u, double sqrt_s, long long N, double* mom)
+//   qedx_rambo_n<n>(const double* u, double sqrt_s, long long N, double* mom)
 // and, for SUM-mode FP64 variants, the gradient kernel
-//   qedx_grad(const double* u, double sqrt_s, long long N, double* logm2, double* grad)
-// grad_lanes / grad_block receive the launch shape of qedx_grad (0 if the
+//   qedx_grad_n<n>(const double* u, double sqrt_s, long long N, double* logm2, double* grad)
+// grad_lanes / grad_block receive the launch shape of qedx_grad_n<n> (0 if the
 // module has no gradient kernel).
 std::string emit_aux_module(const Process& proc, const Variant& v, int n, int* grad_lanes, int* grad_block);
 

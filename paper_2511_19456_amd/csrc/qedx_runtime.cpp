@@ -311,6 +311,15 @@ static qed_status make_variant(int n, qed_hel_mode mode, qed_precision prec, con
   return QED_OK;
 }
 
+// Symbol of the eval kernel: one name per (process, mode, precision, rewrite),
+// so profiles tell the kernels of different processes apart.
+static std::string eval_kernel_name(int n, qed_hel_mode mode, qed_precision prec, int rewrite) {
+  std::string k = "qedx_eval_n" + std::to_string(n) + (mode == QED_HEL_SUM ? "_sum" : "_pp") +
+                  (prec == QED_FP64 ? "_fp64" : "_fp32c");
+  if (rewrite) k += "_d" + std::to_string(rewrite);
+  return k;
+}
+
 static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* qv, Variant& v,
                                Process& proc, std::string& src, qed_info& info) {
   if (n < 1 || n > 6) return fail(QED_ERR_UNSUPPORTED, "n must be in 1..6");
@@ -330,7 +339,7 @@ static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, con
     info.nodes_reduced = (int64_t)d.nodes.size();
     auto t0 = std::chrono::steady_clock::now();
     EmitStats st;
-    src = emit_eval_kernel(d, v, "qedx_eval", &st);
+    src = emit_eval_kernel(d, v, eval_kernel_name(n, mode, prec, v.rewrite), &st);
     info.create_ms_emit = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     info.n_V = st.n_V;
     info.n_S1 = st.n_S1;
@@ -347,6 +356,7 @@ static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, con
   info.block = v.block;
   std::string tag = variant_tag(v, n, 1);
   snprintf(info.kernel_tag, sizeof info.kernel_tag, "%s", tag.c_str());
+  snprintf(info.kernel_name, sizeof info.kernel_name, "%s", eval_kernel_name(n, mode, prec, v.rewrite).c_str());
   return QED_OK;
 }
 
@@ -424,7 +434,7 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   snprintf(p->info.code_hash, sizeof p->info.code_hash, "%s", meta.hash.c_str());
   auto t0 = std::chrono::steady_clock::now();
   HIPCHK(hipModuleLoadData(&p->mod, co.data()));
-  HIPCHK(hipModuleGetFunction(&p->f_eval, p->mod, "qedx_eval"));
+  HIPCHK(hipModuleGetFunction(&p->f_eval, p->mod, p->info.kernel_name));
   // auxiliary module: RAMBO (all processes) and the gradient kernel
   std::string asrc;
   try {
@@ -440,8 +450,9 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   if (s) return s;
   p->info.create_ms_compile += ams;
   HIPCHK(hipModuleLoadData(&p->mod_aux, aco.data()));
-  HIPCHK(hipModuleGetFunction(&p->f_rambo, p->mod_aux, "qedx_rambo"));
-  if (hipModuleGetFunction(&p->f_grad, p->mod_aux, "qedx_grad") != hipSuccess) p->f_grad = nullptr;
+  const std::string ns = std::to_string(n);
+  HIPCHK(hipModuleGetFunction(&p->f_rambo, p->mod_aux, ("qedx_rambo_n" + ns).c_str()));
+  if (hipModuleGetFunction(&p->f_grad, p->mod_aux, ("qedx_grad_n" + ns).c_str()) != hipSuccess) p->f_grad = nullptr;
   (void)hipGetLastError();
   p->info.create_ms_load = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = p.release();

@@ -92,6 +92,7 @@ class QedProcess:
         d = {k: getattr(inf, k) for k, _ in QedInfo._fields_}
         d["kernel_tag"] = inf.kernel_tag.decode()
         d["code_hash"] = inf.code_hash.decode()
+        d["kernel_name"] = inf.kernel_name.decode()
         return d
 
     def eval(self, momenta: torch.Tensor, hel: Optional[torch.Tensor] = None,

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_emitted_source_is_self_contained():
     src = Q.emit_source(2, "sum", "fp64")
-    assert 'extern "C" __global__' in src and "qedx_eval" in src
+    assert 'extern "C" __global__' in src and "qedx_eval_n" in src
     assert "#include \"" not in src  # device header is inlined
     src = Q.emit_source(5, "per_point", "fp32c")
     assert "comp_acc" in src and "qx::dot<float>" in src

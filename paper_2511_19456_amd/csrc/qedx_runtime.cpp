@@ -320,6 +320,12 @@ static std::string eval_kernel_name(int n, qed_hel_mode mode, qed_precision prec
   return k;
 }
 
+// The auxiliary module (RAMBO, gradient) depends on the process, mode and
+// precision only, not on the eval kernel's shape: one cache entry per process.
+static std::string aux_tag(int n, qed_hel_mode mode, qed_precision prec) {
+  return "aux_n" + std::to_string(n) + (mode == QED_HEL_SUM ? "_sum" : "_pp") + (prec == QED_FP64 ? "_fp64" : "_fp32c");
+}
+
 static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* qv, Variant& v,
                                Process& proc, std::string& src, qed_info& info) {
   if (n < 1 || n > 6) return fail(QED_ERR_UNSUPPORTED, "n must be in 1..6");
@@ -399,7 +405,7 @@ extern "C" qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec,
     } catch (const std::exception& e) {
       return fail(QED_ERR_INVALID_ARG, std::string("aux emit: ") + e.what());
     }
-    std::string atag = std::string("aux_") + info.kernel_tag;
+    std::string atag = aux_tag(n, mode, prec);
     s = get_code_object(atag, asrc, co, meta, hit, ms2);
     if (s) return s;
   }
@@ -446,7 +452,7 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   KernelMeta am;
   bool ahit;
   double ams;
-  s = get_code_object(std::string("aux_") + p->info.kernel_tag, asrc, aco, am, ahit, ams);
+  s = get_code_object(aux_tag(n, mode, prec), asrc, aco, am, ahit, ams);
   if (s) return s;
   p->info.create_ms_compile += ams;
   HIPCHK(hipModuleLoadData(&p->mod_aux, aco.data()));

@@ -97,6 +97,7 @@ struct Emitter {
   // kTile streamed currents -- register pressure is then the accumulators,
   // one tile and one held current.
   std::map<int, std::string> alias;
+  bool amp_store = false;  // body() also stores every configuration's amplitude
   bool stage() const { return (v.order & 16) != 0; }
   int lds_slots = 0;
   static constexpr int kTile = 4;
@@ -453,6 +454,11 @@ struct Emitter {
     }
     // |A|^2, summed over the enumerated configurations (HelSum) or single
     for (size_t a = 0; a < sums.size(); ++a) {
+      if (amp_store) {
+        // amplitude of configuration hc | (this Sum's enumerated bits) to amp[2h][N], amp[2h+1][N]
+        os << ind << "if (pt < N) { const unsigned hh = hc | " << d.nodes[sums[a]].cfg << "u; amp[(2 * hh) * N + pt] = A"
+           << a << ".r; amp[(2 * hh + 1) * N + pt] = A" << a << ".i; }\n";
+      }
       if (v.prec == PREC_F64) {
         os << ind << "acc += A" << a << ".r * A" << a << ".r + A" << a << ".i * A" << a << ".i;\n";
       } else {
@@ -476,6 +482,15 @@ struct Emitter {
   std::set<int> leafJ;
 
   bool final_particle(int p) const { return p == pr.i_eout || (p > pr.i_eout); }
+
+  // momentum-gradient accumulator of (particle p, component mu): a register,
+  // or a per-lane LDS slot when gm_in_lds is set (keeps it out of the
+  // register file during the adjoint sweep)
+  bool gm_in_lds = false;
+  std::string gmref(int p, int mu) const {
+    if (!gm_in_lds) return "gm" + std::to_string(p) + "_" + std::to_string(mu);
+    return "qx_gm[" + std::to_string((4 * p + mu) * v.block) + " + threadIdx.x]";
+  }
 
   void collect_block(const std::vector<int>& dk) {
     blk.clear();
@@ -514,11 +529,11 @@ struct Emitter {
     os << ind << "  qx::prop_from_vjp(" << m << "0, " << m << "1, " << m << "2, " << m << "3, Kl0, Kl1, Kl2, Kl3, "
        << (side == 0 ? "1.0" : "-1.0") << ", 1.0, gq, gp, gK);\n";
     if (final_particle(pe))
-      for (int mu = 0; mu < 4; ++mu) os << ind << "  gm" << pe << "_" << mu << " += gp[" << mu << "];\n";
+      for (int mu = 0; mu < 4; ++mu) os << ind << "  " << gmref(pe, mu) << " += gp[" << mu << "];\n";
     for (int a = 0; a < pr.P; ++a)
       if (((mask >> a) & 1) && final_particle(pr.photon_particle[a]))
         for (int mu = 0; mu < 4; ++mu)
-          os << ind << "  gm" << pr.photon_particle[a] << "_" << mu << (pr.photon_sign[a] > 0 ? " += " : " -= ")
+          os << ind << "  " << gmref(pr.photon_particle[a], mu) << (pr.photon_sign[a] > 0 ? " += " : " -= ")
              << "gK[" << mu << "];\n";
     os << ind << "}\n";
   }
@@ -606,7 +621,7 @@ struct Emitter {
           std::string m = "m" + std::to_string(pr.i_eout) + "_";
           os << ind << "{ double g[4]; qx::ubar_vjp(" << m << "0, " << m << "1, " << m << "2, " << m << "3, "
              << hel_expr(n) << ", 1.0, w" << r << ", g);\n";
-          for (int mu = 0; mu < 4; ++mu) os << ind << "  gm" << pr.i_eout << "_" << mu << " += g[" << mu << "];\n";
+          for (int mu = 0; mu < 4; ++mu) os << ind << "  " << gmref(pr.i_eout, mu) << " += g[" << mu << "];\n";
           os << ind << "}\n";
         }
       }
@@ -619,7 +634,7 @@ struct Emitter {
         os << ind << "{ double g[3]; qx::pol_vjp(" << m << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", ge"
            << x << ", g);\n";
         for (int mu = 1; mu < 4; ++mu)
-          os << ind << "  gm" << n.particle << "_" << mu << " += g[" << (mu - 1) << "];\n";
+          os << ind << "  " << gmref(n.particle, mu) << " += g[" << (mu - 1) << "];\n";
         os << ind << "}\n";
       }
     }
@@ -628,6 +643,7 @@ struct Emitter {
 
   // momenta for a partition-local block, opaque to the compiler
   void block_momenta() {
+    if (mom_src == 2) return;  // momenta already in m<p>_<mu> of the enclosing scope
     if (mom_src == 0) {
       os << ind << "long long pq = ptc;\n" << ind << "asm volatile(\"\" : \"+v\"(pq));\n";
       load_momenta("mom", "N", "pq");
@@ -843,6 +859,108 @@ std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& 
   e.st.flops_per_point *= (double)G * (double)(1 << popc(v.loop_mask));
   if (stats) *stats = e.st;
   return os.str();
+}
+
+// ---------------------------------------------------------------------------
+// Split gradient: amplitude kernel + one adjoint kernel per photon partition
+// ---------------------------------------------------------------------------
+std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* stats) {
+  check_variant(d, v);
+  if (v.mode != HEL_SUM || v.prec != PREC_F64 || (v.order & (8 | 16)) || d.distributed)
+    throw std::invalid_argument("amplitude kernels take SUM, FP64, the node-reduced graph, no loop or LDS schedule");
+  Emitter e(d, v);
+  e.amp_store = true;
+  const Process& pr = d.proc;
+  const int LB = popc(v.lane_mask), G = 1 << LB;
+  std::ostringstream& os = e.os;
+  os << "extern \"C\" __global__ void __launch_bounds__(" << v.block << ")\n" << kname
+     << "(const double* __restrict__ mom, long long N, double* __restrict__ amp, double* __restrict__ logm2, "
+        "double* __restrict__ im2, double* __restrict__ gm)\n{\n";
+  os << "  const long long gid = (long long)blockIdx.x * " << v.block << " + threadIdx.x;\n";
+  os << "  const long long pt = gid >> " << LB << ";\n";
+  os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
+  os << "  const long long ptc = pt < N ? pt : N - 1;\n";
+  if (!e.local()) e.load_momenta("mom", "N", "ptc");
+  os << "  if (pt < N && sub == 0u) {\n";
+  for (int p = 2; p < pr.npart; ++p)
+    for (int mu = 0; mu < 4; ++mu) os << "    gm[" << (4 * p + mu) << " * N + pt] = 0.0;\n";
+  os << "  }\n";
+  os << "  double acc = 0.0;\n";
+  e.lane_work(Emitter::deposit("sub", v.lane_mask));
+  for (int o = 1; o < G; o <<= 1) os << "  acc += __shfl_xor(acc, " << o << ");\n";
+  os << "  if (pt < N && sub == 0u) { logm2[pt] = log(acc); im2[pt] = 1.0 / acc; }\n}\n";
+  e.st.flops_per_point *= (double)G * (double)(1 << popc(v.loop_mask));
+  if (stats) *stats = e.st;
+  return os.str();
+}
+
+std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const std::string& kprefix, int* count,
+                                           EmitStats* stats) {
+  check_variant(d, v);
+  if (v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4) || (v.order & (8 | 16)) || d.distributed)
+    throw std::invalid_argument("adjoint kernels take SUM, FP64, local blocks, the node-reduced graph");
+  const Process& pr = d.proc;
+  const int LB = popc(v.lane_mask), G = 1 << LB;
+  const int nloop = popc(v.loop_mask);
+  std::map<uint32_t, std::vector<int>> part;
+  std::vector<uint32_t> order;
+  {
+    Emitter probe(d, v);
+    probe.partitions(part, order);
+  }
+  std::ostringstream all;
+  EmitStats tot;
+  int t = 0;
+  for (uint32_t key : order) {
+    Emitter e(d, v);
+    e.mom_src = 0;       // momenta reloaded per block from the workspace
+    e.gm_in_lds = true;  // gradient accumulators in per-lane LDS slots
+    std::vector<int> sums = e.sum_nodes();
+    for (size_t a = 0; a < sums.size(); ++a) e.acc_of_sum[sums[a]] = (int)a;
+    std::ostringstream& os = e.os;
+    os << "extern \"C\" __global__ void __launch_bounds__(" << v.block << ")\n" << kprefix << "_" << t
+       << "(const double* __restrict__ mom, const double* __restrict__ amp, const double* __restrict__ im2, "
+          "long long N, double* __restrict__ gm)\n{\n";
+    os << "  __shared__ double qx_gm[" << 4 * pr.npart * v.block << "];\n";
+    os << "  const long long gid = (long long)blockIdx.x * " << v.block << " + threadIdx.x;\n";
+    os << "  const long long pt = gid >> " << LB << ";\n";
+    os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
+    os << "  const long long ptc = pt < N ? pt : N - 1;\n";
+    for (int p = 2; p < pr.npart; ++p)
+      for (int mu = 0; mu < 4; ++mu) os << "  " << e.gmref(p, mu) << " = 0.0;\n";
+    os << "  const double iM2 = im2[ptc];\n";
+    os << "  const unsigned hrt = " << Emitter::deposit("sub", v.lane_mask) << ";\n";
+    os << "  #pragma unroll 1\n  for (unsigned lp = 0; lp < " << (1u << nloop) << "u; ++lp) {\n";
+    os << "    const unsigned hc = hrt | " << Emitter::deposit("lp", v.loop_mask) << ";\n";
+    e.ind = "    ";
+    // seeds: conj(A_h) / |M|^2 of this iteration's configurations
+    for (size_t a = 0; a < sums.size(); ++a) {
+      os << e.ind << "const unsigned h" << a << " = hc | " << d.nodes[sums[a]].cfg << "u;\n";
+      os << e.ind << "const qx::cx<double> c" << a << " = {amp[(2 * h" << a << ") * N + ptc] * iM2, -amp[(2 * h" << a
+         << " + 1) * N + ptc] * iM2};\n";
+    }
+    e.grad_block(key, part[key]);
+    e.ind = "  ";
+    os << "  }\n";
+    for (int p = 2; p < pr.npart; ++p)
+      for (int mu = 0; mu < 4; ++mu) {
+        os << "  double gm" << p << "_" << mu << " = " << e.gmref(p, mu) << ";\n";
+        for (int o = 1; o < G; o <<= 1)
+          os << "  gm" << p << "_" << mu << " += __shfl_xor(gm" << p << "_" << mu << ", " << o << ");\n";
+      }
+    os << "  if (pt < N && sub == 0u) {\n";
+    for (int p = 2; p < pr.npart; ++p)
+      for (int mu = 0; mu < 4; ++mu)
+        os << "    gm[" << (4 * p + mu) << " * N + pt] += gm" << p << "_" << mu << ";\n";
+    os << "  }\n}\n";
+    tot.flops_per_point += e.st.flops_per_point * (double)G * (double)(1 << nloop);
+    std::string ks = os.str();
+    all << ks;
+    ++t;
+  }
+  if (count) *count = t;
+  if (stats) *stats = tot;
+  return all.str();
 }
 
 std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* stats) {

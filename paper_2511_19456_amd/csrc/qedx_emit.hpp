@@ -57,6 +57,21 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
 // the caller prepends it.
 std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* st);
 
+// Split gradient (SUM, FP64), for processes whose fused gradient kernel would
+// not fit the register file.  The amplitude kernel stores every
+// configuration's amplitude, log |M|^2 and 1/|M|^2, and zeroes the momentum
+// gradient rows of the final-state particles:
+//   extern "C" __global__ void <kname>(const double* mom, long long N,
+//       double* amp /*[2H][N]*/, double* logm2, double* im2, double* gm /*[4 npart][N]*/)
+std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* st);
+// One kernel per photon partition, <kprefix>_<t>, t = 0..*count-1: the
+// partition's adjoint sweep for every configuration (seeds conj(A_h)/|M|^2
+// read from amp), adding its momentum gradient into gm:
+//   extern "C" __global__ void <kprefix>_<t>(const double* mom, const double* amp,
+//       const double* im2, long long N, double* gm)
+std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const std::string& kprefix, int* count,
+                                           EmitStats* st);
+
 // Device function text of one process body (used by the mixed batch module):
 //   __device__ double <fname>(const double* mom, long long N, long long pt,
 //                             unsigned hrt)

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/qedx.h"
 #include "qedx_dag.hpp"
@@ -30,8 +31,18 @@ struct qed_process {
   hipFunction_t f_grad = nullptr;
   int grad_block = 256;
   int grad_lanes = 0;
+  // split gradient (n = 4, 5): kernels and a workspace grown on first use
+  int grad_split = 0, amp_lanes = 0, adj_lanes = 0;
+  hipFunction_t f_grambo = nullptr, f_gamp = nullptr, f_grvjp = nullptr;
+  std::vector<hipFunction_t> f_gadj;
+  double* ws = nullptr;
+  size_t ws_bytes = 0;
   std::string eval_src;
   ~qed_process() {
+    if (ws) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(ws);
+    }
     if (mod) (void)hipModuleUnload(mod);
     if (mod_aux) (void)hipModuleUnload(mod_aux);
   }

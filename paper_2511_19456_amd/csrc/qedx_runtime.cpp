@@ -401,7 +401,7 @@ extern "C" qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec,
   if (with_aux) {
     std::string asrc;
     try {
-      asrc = emit_aux_module(proc, v, n, nullptr, nullptr);
+      asrc = emit_aux_module(proc, v, n, nullptr);
     } catch (const std::exception& e) {
       return fail(QED_ERR_INVALID_ARG, std::string("aux emit: ") + e.what());
     }
@@ -444,7 +444,14 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   // auxiliary module: RAMBO (all processes) and the gradient kernel
   std::string asrc;
   try {
-    asrc = emit_aux_module(p->proc, p->var, n, &p->grad_lanes, &p->grad_block);
+    AuxInfo ai;
+    asrc = emit_aux_module(p->proc, p->var, n, &ai);
+    p->grad_lanes = ai.grad_lanes;
+    p->grad_block = ai.grad_block ? ai.grad_block : 256;
+    p->grad_split = ai.split;
+    p->amp_lanes = ai.amp_lanes;
+    p->adj_lanes = ai.adj_lanes;
+    p->f_gadj.assign(ai.n_adj, nullptr);
   } catch (const std::exception& e) {
     return fail(QED_ERR_INVALID_ARG, std::string("aux emit: ") + e.what());
   }
@@ -459,6 +466,13 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   const std::string ns = std::to_string(n);
   HIPCHK(hipModuleGetFunction(&p->f_rambo, p->mod_aux, ("qedx_rambo_n" + ns).c_str()));
   if (hipModuleGetFunction(&p->f_grad, p->mod_aux, ("qedx_grad_n" + ns).c_str()) != hipSuccess) p->f_grad = nullptr;
+  if (p->grad_split) {
+    HIPCHK(hipModuleGetFunction(&p->f_grambo, p->mod_aux, ("qedx_grambo_n" + ns).c_str()));
+    HIPCHK(hipModuleGetFunction(&p->f_gamp, p->mod_aux, ("qedx_gamp_n" + ns).c_str()));
+    HIPCHK(hipModuleGetFunction(&p->f_grvjp, p->mod_aux, ("qedx_grvjp_n" + ns).c_str()));
+    for (size_t t = 0; t < p->f_gadj.size(); ++t)
+      HIPCHK(hipModuleGetFunction(&p->f_gadj[t], p->mod_aux, ("qedx_gadj_n" + ns + "_" + std::to_string(t)).c_str()));
+  }
   (void)hipGetLastError();
   p->info.create_ms_load = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = p.release();
@@ -519,12 +533,60 @@ extern "C" qed_status qed_eval_grad(const qed_process* p, const double* uniforms
   if (hel) return fail(QED_ERR_INVALID_ARG, "hel must be NULL");
   if (N < 0) return fail(QED_ERR_INVALID_ARG, "N < 0");
   if (!(sqrt_s > 1.0) || !std::isfinite(sqrt_s)) return fail(QED_ERR_INVALID_ARG, "sqrt_s must exceed m = 1");
-  if (!p->f_grad) return fail(QED_ERR_UNSUPPORTED, "no gradient kernel for this process variant");
+  if (!p->f_grad && !p->grad_split) return fail(QED_ERR_UNSUPPORTED, "no gradient kernel for this process variant");
   if (N == 0) return QED_OK;
   if (!uniforms || !out_logm2 || !out_grad) return fail(QED_ERR_INVALID_ARG, "NULL buffer");
-  long long n = (long long)N;
-  void* args[] = {(void*)&uniforms, (void*)&sqrt_s, (void*)&n, (void*)&out_logm2, (void*)&out_grad};
-  return launch(p->f_grad, N * (int64_t)p->grad_lanes, p->grad_block, stream, args);
+  if (!p->grad_split) {
+    long long n = (long long)N;
+    void* args[] = {(void*)&uniforms, (void*)&sqrt_s, (void*)&n, (void*)&out_logm2, (void*)&out_grad};
+    return launch(p->f_grad, N * (int64_t)p->grad_lanes, p->grad_block, stream, args);
+  }
+  // Split gradient over chunks of C points.  Workspace per point: momenta and
+  // momentum gradient [4(n+3)] each, amplitudes [2 * 2^(n+3)], 1/|M|^2.
+  const int npart = p->n + 3;
+  const int64_t H = (int64_t)1 << npart;
+  const int64_t per_pt = 8 * (2 * 4 * (int64_t)npart + 2 * H + 1);
+  int64_t C = (int64_t)1 << 20;
+  while (C > 256 && C * per_pt > ((int64_t)320 << 20)) C >>= 1;
+  if (C > N) C = N;
+  const size_t need = (size_t)(C * per_pt);
+  qed_process* pm = const_cast<qed_process*>(p);  // the workspace is the only mutable state
+  if (pm->ws_bytes < need) {
+    if (pm->ws) {
+      HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+      (void)hipFree(pm->ws);
+      pm->ws = nullptr;
+      pm->ws_bytes = 0;
+    }
+    if (hipMalloc((void**)&pm->ws, need) != hipSuccess) {
+      pm->ws = nullptr;
+      return fail(QED_ERR_OOM, "gradient workspace allocation failed");
+    }
+    pm->ws_bytes = need;
+  }
+  for (int64_t off = 0; off < N; off += C) {
+    long long cnt = (long long)std::min<int64_t>(C, N - off);
+    long long ldu = (long long)N;
+    double* mom = pm->ws;
+    double* gm = mom + 4 * (int64_t)npart * cnt;
+    double* amp = gm + 4 * (int64_t)npart * cnt;
+    double* im2 = amp + 2 * H * cnt;
+    const double* u = uniforms + off;
+    double* lg = out_logm2 + off;
+    double* gr = out_grad + off;
+    qed_status st;
+    void* a1[] = {(void*)&u, (void*)&ldu, (void*)&sqrt_s, (void*)&cnt, (void*)&mom};
+    if ((st = launch(p->f_grambo, cnt, 256, stream, a1))) return st;
+    void* a2[] = {(void*)&mom, (void*)&cnt, (void*)&amp, (void*)&lg, (void*)&im2, (void*)&gm};
+    if ((st = launch(p->f_gamp, cnt * (int64_t)p->amp_lanes, 256, stream, a2))) return st;
+    for (hipFunction_t f : p->f_gadj) {
+      void* a3[] = {(void*)&mom, (void*)&amp, (void*)&im2, (void*)&cnt, (void*)&gm};
+      if ((st = launch(f, cnt * (int64_t)p->adj_lanes, 256, stream, a3))) return st;
+    }
+    void* a4[] = {(void*)&u, (void*)&ldu, (void*)&sqrt_s, (void*)&cnt, (void*)&gm, (void*)&gr, (void*)&ldu};
+    if ((st = launch(p->f_grvjp, cnt, 256, stream, a4))) return st;
+  }
+  return QED_OK;
 }
 
 // ---------------------------------------------------------------------------

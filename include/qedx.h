@@ -28,8 +28,10 @@
  *    and return without synchronising.  Launch failures return QED_ERR_HIP.
  *  - On any error the function returns a nonzero status, writes nothing to
  *    the outputs, and qed_last_error() returns a message (thread-local).
- *  - N == 0 is a valid no-op.  No entry point allocates device memory except
- *    qed_batch_plan_create (its tile table).
+ *  - N == 0 is a valid no-op.  Device memory is allocated only by
+ *    qed_batch_plan_create (its tile table and counter) and by qed_eval_grad
+ *    for n >= 4 (a workspace owned by the process handle, grown on demand and
+ *    freed by qed_process_destroy).
  */
 #ifndef QEDX_H
 #define QEDX_H
@@ -132,9 +134,16 @@ qed_status qed_rambo(const qed_process* p, const double* uniforms, double sqrt_s
 
 /* log|M|^2 (SUM mode processes) and its gradient with respect to the RAMBO
  * uniforms: out_logm2 [N], out_grad [4(n+1)][N] (row = uniform index), both
- * float64 device buffers.  Forward RAMBO, forward graph, adjoint graph and
- * adjoint RAMBO run in one kernel; nothing is stored between passes.
- * `hel` must be NULL.  UNSUPPORTED for PER_POINT or FP32C processes. */
+ * float64 device buffers.  The gradient is the reverse sweep of the graph:
+ * currents are recomputed from their parents on the way back, not stored.
+ * n <= 3: forward RAMBO, forward graph, adjoint graph and adjoint RAMBO in one
+ * kernel.  n = 4, 5: per chunk of points, RAMBO into a workspace, one kernel
+ * storing every configuration's amplitude A_h and 1/|M|^2 (the adjoint seeds
+ * conj(A_h)/|M|^2), one adjoint kernel per photon partition, and the RAMBO
+ * adjoint; the workspace (about 2.5 KB per point at n = 4, 320 MB at most)
+ * belongs to the process, so calls on one process must not overlap on
+ * different streams.  `hel` must be NULL.  UNSUPPORTED for PER_POINT or FP32C
+ * processes and for n = 6.  QED_ERR_OOM if the workspace cannot be allocated. */
 qed_status qed_eval_grad(const qed_process* p, const double* uniforms, double sqrt_s, const uint32_t* hel,
                          int64_t N, double* out_logm2, double* out_grad, void* stream);
 

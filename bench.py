@@ -123,7 +123,7 @@ def rel_err_stats(a, b, per_point=False):
         den = torch.clamp(den, min=1e-3 * den.median().item())
     r = ((a - b).abs() / den).double()
     q = torch.quantile(r[: 1 << 20].float(), torch.tensor([0.5, 0.99], device=r.device)).tolist()
-    return {"max": r.max().item(), "p99": q[1], "median": q[0]}
+    return {"max": r.max().item(), "p99": q[1], "median": q[0], "frac_above_1e-4": (r > 1e-4).double().mean().item()}
 
 
 def main():

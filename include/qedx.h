@@ -173,8 +173,9 @@ qed_status qed_batch_plan_destroy(qed_batch_plan* plan);
  * persistent grid, 64-point chunks per tile. */
 qed_status qed_batch_info(const qed_batch_plan* plan, int64_t* ntiles, int* grid, int* chunk);
 /* Ahead-of-time build of the batch module for the per-point processes
- * n_list[0..count) with default kernel shapes (no GPU needed). */
-qed_status qed_batch_prebuild(const int* n_list, int count, qed_precision prec, double* compile_ms);
+ * n_list[0..count) with default kernel shapes, node-reduced (rewrite = 0) or
+ * distributed (rewrite = 1) (no GPU needed). */
+qed_status qed_batch_prebuild(const int* n_list, int count, qed_precision prec, int rewrite, double* compile_ms);
 
 /* Last error message of the calling thread ("" if none). */
 const char* qed_last_error(void);

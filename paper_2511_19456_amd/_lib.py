@@ -59,7 +59,7 @@ SIGNATURES = {
     "qed_batch_launch": (c_int, [c_void_p, c_void_p]),
     "qed_batch_plan_destroy": (c_int, [c_void_p]),
     "qed_batch_info": (c_int, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
-    "qed_batch_prebuild": (c_int, [ctypes.POINTER(c_int), c_int, c_int, ctypes.POINTER(c_double)]),
+    "qed_batch_prebuild": (c_int, [ctypes.POINTER(c_int), c_int, c_int, c_int, ctypes.POINTER(c_double)]),
     "qed_last_error": (c_char_p, []),
     "qed_cache_dir": (c_char_p, []),
     "qed_graph_counts": (c_int, [c_int, c_int, c_uint32, c_int, c_int, ctypes.POINTER(c_int64)]),

@@ -92,7 +92,8 @@ DEFAULT_KERNELS = [
     (3, 0, 1, dict(rewrite=1)), (5, 1, 1, dict(rewrite=1)),
     # kernel shapes the parity tests exercise
     (3, 0, 0, dict(lane_bits=7)), (3, 0, 0, dict(lane_bits=5, order=4)), (3, 0, 0, dict(lane_bits=63, order=4)),
-    (3, 1, 0, dict(order=4)),
+    (3, 1, 0, dict(order=4)), (3, 0, 0, dict(lane_bits=5, order=16)), (3, 0, 0, dict(lane_bits=5, loop_bits=2, order=32)),
+    (3, 1, 0, dict(order=24)),
 ]
 
 
@@ -127,20 +128,20 @@ def prebuild_kernels(kernels=DEFAULT_KERNELS, jobs: int = 8, verbose: bool = Tru
     return out
 
 
-BATCH_MODULES = [((1, 2, 3, 4, 5, 6), 0), ((1, 2, 3, 4, 5, 6), 1)]
+BATCH_MODULES = [((1, 2, 3, 4, 5, 6), 0, 0), ((1, 2, 3, 4, 5, 6), 1, 0), ((1, 2, 3, 4, 5, 6), 0, 1)]
 
 
 def prebuild_batches(verbose: bool = True) -> None:
     lib = ctypes.CDLL(LIB)
-    lib.qed_batch_prebuild.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+    lib.qed_batch_prebuild.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_double)]
     lib.qed_last_error.restype = ctypes.c_char_p
 
     def one(spec):
-        ns, prec = spec
+        ns, prec, rewrite = spec
         arr = (ctypes.c_int * len(ns))(*ns)
         ms = ctypes.c_double(0)
-        rc = lib.qed_batch_prebuild(arr, len(ns), prec, ctypes.byref(ms))
+        rc = lib.qed_batch_prebuild(arr, len(ns), prec, rewrite, ctypes.byref(ms))
         return spec, rc, ms.value, lib.qed_last_error().decode() if rc else ""
 
     with cf.ThreadPoolExecutor(max_workers=len(BATCH_MODULES)) as ex:

@@ -152,6 +152,7 @@ struct Emitter {
   }
 
   bool local() const { return (v.order & 4) != 0 && !slot; }
+  bool loop_local() const { return (v.order & 32) != 0 && v.loop_mask != 0 && !local() && !slot; }
 
   // scheduling fence: keeps LLVM's machine scheduler from moving work across
   void fence(int level) {
@@ -684,6 +685,9 @@ struct Emitter {
       os << ind << "for (unsigned lp = 0; lp < " << (1u << nloop) << "u; ++lp) {\n";
       ind = "    ";
       os << ind << "const unsigned hc = hrt | " << deposit("lp", v.loop_mask) << ";\n";
+      // order flag 32: momenta reloaded per iteration through an opaque index,
+      // so nothing is hoisted out of the loop and kept live across it
+      if (loop_local()) block_momenta();
       body();
       ind = "  ";
       os << ind << "}\n";
@@ -737,7 +741,7 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   os << "  const long long pt = gid >> " << LB << ";\n";
   os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
   os << "  const long long ptc = pt < N ? pt : N - 1;\n";
-  if (!e.local() && !e.slot) e.load_momenta("mom", "N", "ptc");
+  if (!e.local() && !e.slot && !e.loop_local()) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
   std::string hrt = v.mode == HEL_PER_POINT ? "hel[ptc]" : Emitter::deposit("sub", v.lane_mask);
   e.lane_work(hrt);

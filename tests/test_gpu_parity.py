@@ -100,13 +100,17 @@ def test_empty_and_single_point():
 # ---------------------------------------------------------------------------
 # schedule variants must not change results
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("mode,lanes,order", [("sum", 7, 0), ("sum", 5, 4), ("sum", 63, 4), ("per_point", 0, 4)])
-def test_schedule_variants_n3(mode, lanes, order):
+# order flags: 4 partition-local blocks, 8 partition loop, 16 LDS staging of
+# the held side, 32 momenta reloaded per loop iteration
+@pytest.mark.parametrize("mode,lanes,order,loop", [("sum", 7, 0, 0), ("sum", 5, 4, 0), ("sum", 63, 4, 0),
+                                                   ("per_point", 0, 4, 0), ("sum", 5, 16, 0), ("sum", 5, 32, 2),
+                                                   ("per_point", 0, 24, 0)])
+def test_schedule_variants_n3(mode, lanes, order, loop):
     from paper_2511_19456_amd.qedx import make_variant
     n, sqrt_s, N = 3, 10.0, 517
     u, hel = inputs.rambo_inputs(21, n, N, with_helicities=True)
     ref_mom = O.momenta_soa_from_uniforms(u, sqrt_s, n)
-    p = _proc(n, mode, "fp64", make_variant(lane_bits=lanes, order=order))
+    p = _proc(n, mode, "fp64", make_variant(lane_bits=lanes, loop_bits=loop, order=order))
     h = torch.as_tensor(hel.astype(np.int32), device=DEV) if mode == "per_point" else None
     got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV), h).cpu().numpy()
     ref = O.m2(ref_mom, n, mode, hel).numpy()
@@ -229,15 +233,15 @@ def test_per_point_n6_fp64(n, sqrt_s, N):
     assert _per_point_err(got, ref, scale).max() < 1e-10
 
 
-@pytest.mark.parametrize("prec,tile", [("fp64", 128), ("fp64", 0), ("fp32c", 0)])
-def test_mixed_batch_matches_per_process_and_oracle(prec, tile):
-    from paper_2511_19456_amd.qedx import BatchPlan
+@pytest.mark.parametrize("prec,tile,rewrite", [("fp64", 128, 0), ("fp64", 0, 0), ("fp32c", 0, 0), ("fp64", 256, 1)])
+def test_mixed_batch_matches_per_process_and_oracle(prec, tile, rewrite):
+    from paper_2511_19456_amd.qedx import BatchPlan, make_variant
     spec = [(1, 1000, 6.0), (2, 3 * 64 + 5, 9.0), (3, 2500, 12.0), (4, 777, 15.0), (5, 301, 20.0),
             (6, 130, 25.0), (3, 0, 10.0)]
     segs, refs, checks = [], [], []
     for k, (n, N, rs) in enumerate(spec):
         u, hel = inputs.rambo_inputs(40 + k, n, N, with_helicities=True)
-        p = _proc(n, "per_point", prec)
+        p = _proc(n, "per_point", prec, make_variant(rewrite=1) if rewrite else None)
         mom = p.rambo(torch.as_tensor(u, device=DEV), rs)
         h = torch.as_tensor(hel.astype(np.int32), device=DEV)
         out = torch.full((N,), float("nan"), dtype=torch.float64, device=DEV)

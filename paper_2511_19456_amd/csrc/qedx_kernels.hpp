@@ -29,8 +29,8 @@ struct AuxInfo {
 //      qedx_grvjp_n<n>(u, ldu, sqrt_s, N, gm, grad, ldg)  RAMBO adjoint.
 std::string emit_aux_module(const Process& proc, const Variant& v, int n, AuxInfo* info);
 
-// Kernel shape of the gradient: every photon polarisation and as many
-// electron spins as fit on 64 lanes; the rest enumerated in the graph.
+// Kernel shape of the fused gradient (n <= 3): every photon polarisation and
+// as many electron spins as fit on 64 lanes; the rest enumerated in the graph.
 Variant grad_variant(const Process& proc);
 
 }  // namespace qedx

@@ -319,6 +319,45 @@ def extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom_n3):
     _leg(legs, "mixed_n1to6_fp64", want, mixed("fp64"))
     _leg(legs, "mixed_n1to6_fp32c", want, mixed("fp32c"))
 
+    def reduction_sweep():
+        """The paper's reduction experiment (Sec. III-D, III-E) on this GPU:
+        n = 4, one configuration per point, the unsplit graph after k of the
+        single node reductions (seeded random order), each emitted as one
+        straight-line kernel; plus the full pipeline (reduction, join split,
+        reduction, partition loop).  Speedup S(N) = t_e N / (t'_e N + t_o) and
+        break-even N = t_o / (t_e - t'_e), t_o = host time of the reductions."""
+        from paper_2511_19456_amd.qedx import graph_partial, make_variant, reduction_check
+        n, seed = 4, 1
+        total = reduction_check(n, seed, enum_mask=0, split=2)[2]
+        t0 = time.perf_counter()
+        graph_partial(n, total, seed)
+        t_o = time.perf_counter() - t0
+        ks = [0, total // 4, total // 2, 3 * total // 4, total]
+        N = 1 << 20
+        u, h = inputs.rambo_inputs(3, n, N, with_helicities=True)
+        hd = torch.as_tensor(h.astype(np.int32), device=dev)
+        rows = []
+        base = {}
+        for k in ks + ["full"]:
+            v = None if k == "full" else make_variant(partial_steps=k, partial_seed=seed)
+            p = QedProcess(n, "per_point", "fp64", v)
+            m = p.rambo(torch.as_tensor(u, device=dev), 15.0)
+            row = {"k": k, "nodes": p.info()["nodes_reduced"], "scratch": p.info()["scratch_bytes"]}
+            for Nt in (1 << 14, N):
+                mm, hh = m[:, :Nt].contiguous(), hd[:Nt].contiguous()
+                o = torch.empty(Nt, dtype=torch.float64, device=dev)
+                ms = time_launches(lambda: p.eval(mm, hh, out=o), steps, 2)
+                row[f"ms_{Nt}"] = ms
+                if k == 0:
+                    base[Nt] = ms
+                row[f"speedup_{Nt}"] = base[Nt] / ms
+            te, tk = base[N] / N * 1e-3, row[f"ms_{N}"] / N * 1e-3
+            row["break_even_N"] = t_o / (te - tk) if te > tk else None
+            rows.append(row)
+        return {"process": "e- gamma -> e- 4gamma, one configuration per point", "total_reductions": total,
+                "t_o_s": t_o, "rows": rows}
+    _leg(legs, "reduction_sweep_n4", want, reduction_sweep)
+
     def grad():
         wl = inputs.WORKLOADS["grad_n4_sum_rs15_2p18"]
         u, _ = inputs.rambo_inputs(wl["seed"], wl["n"], wl["N"])

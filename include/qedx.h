@@ -88,6 +88,13 @@ typedef struct {
                            diagram sum becomes one join per photon partition and the currents
                            one per photon subset.  Same result up to rounding.  The gradient
                            kernel always uses the node-reduced graph. */
+  int32_t partial;      /* nonzero: instead of the full pipeline, the paper's unsplit graph
+                           after only the first partial_steps single node reductions in the
+                           random order seeded by partial_seed (0 steps = unreduced), emitted
+                           as one straight-line block; for the reduction experiment of
+                           Sec. III-D (kernel time against the number of reductions). */
+  int32_t partial_steps;
+  uint32_t partial_seed;
 } qed_variant;
 
 typedef struct {
@@ -202,6 +209,13 @@ qed_status qed_graph_interpret(int n, int n_in, uint32_t enum_mask, int split, i
  * reductions in *steps. */
 qed_status qed_graph_reduction_check(int n, int n_in, uint32_t enum_mask, int split, uint64_t seed, char* canon_a,
                                      char* canon_b, int64_t buflen, int64_t* steps);
+/* The graph of the reduction experiment (Sec. III-D): the unreduced graph
+ * for n outgoing photons, one configuration per point, after the first
+ * `steps` single node reductions in the random order seeded by `seed`.
+ * Writes counts[10] (as qed_graph_counts) if non-NULL and, for N points
+ * (mom host [N][4(n+3)], hel host [N] or NULL), the interpreted |A|^2. */
+qed_status qed_graph_partial(int n, int split, int64_t steps, uint64_t seed, const double* mom, const uint32_t* hel,
+                             int64_t N, double* out, int64_t* counts);
 /* Generated HIP source of the eval kernel for a variant (for inspection and
  * for prebuilding the cache); writes at most buflen bytes, returns the full
  * length in *len. */

@@ -9,7 +9,7 @@ been built.
 import importlib
 
 _API = ("QedProcess", "QedLogM2", "BatchPlan", "make_variant", "graph_counts", "graph_interpret",
-        "graph_metrics", "reduction_check", "emit_source")
+        "graph_metrics", "reduction_check", "emit_source", "graph_partial")
 __all__ = list(_API)
 
 

@@ -26,7 +26,8 @@ FP64, FP32C = 0, 1
 class QedVariant(ctypes.Structure):
     _fields_ = [("lane_bits", c_uint32), ("loop_bits", c_uint32), ("block", ctypes.c_int32),
                 ("split", ctypes.c_int32), ("min_waves", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32)]
+                ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32),
+                ("partial", ctypes.c_int32), ("partial_steps", ctypes.c_int32), ("partial_seed", ctypes.c_uint32)]
 
 
 class QedInfo(ctypes.Structure):
@@ -73,6 +74,8 @@ SIGNATURES = {
                              ctypes.POINTER(c_double)]),
     "qed_graph_grad_interpret": (c_int, [c_int, c_int, c_int, c_void_p, c_int64, c_void_p, c_void_p]),
     "qed_rambo_vjp_host": (c_int, [c_int, c_void_p, c_double, c_void_p, c_int64, c_void_p, c_void_p]),
+    "qed_graph_partial": (c_int, [c_int, c_int, c_int64, ctypes.c_uint64, c_void_p, c_void_p, c_int64, c_void_p,
+                                  ctypes.POINTER(c_int64)]),
     "qed_graph_metrics": (c_int, [c_int, c_int, c_uint32, c_int, c_int, c_int, ctypes.POINTER(c_double),
                                   ctypes.POINTER(c_double)]),
 }

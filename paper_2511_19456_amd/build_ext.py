@@ -76,7 +76,8 @@ def build_library(verbose: bool = False) -> None:
 class QedVariant(ctypes.Structure):
     _fields_ = [("lane_bits", ctypes.c_uint32), ("loop_bits", ctypes.c_uint32), ("block", ctypes.c_int32),
                 ("split", ctypes.c_int32), ("min_waves", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32)]
+                ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32),
+                ("partial", ctypes.c_int32), ("partial_steps", ctypes.c_int32), ("partial_seed", ctypes.c_uint32)]
 
 
 # (n, mode, precision[, variant fields]) built ahead of time: SUM 0 / PER_POINT 1;
@@ -94,6 +95,11 @@ DEFAULT_KERNELS = [
     (3, 0, 0, dict(lane_bits=7)), (3, 0, 0, dict(lane_bits=5, order=4)), (3, 0, 0, dict(lane_bits=63, order=4)),
     (3, 1, 0, dict(order=4)), (3, 0, 0, dict(lane_bits=5, order=16)), (3, 0, 0, dict(lane_bits=5, loop_bits=2, order=32)),
     (3, 1, 0, dict(order=24)),
+    # reduction experiment (Sec. III-D): n = 4, one configuration per point, unsplit graph after
+    # k of the 280 single node reductions (seeded order 1)
+    (4, 1, 0, dict(partial_steps=0, partial_seed=1)), (4, 1, 0, dict(partial_steps=70, partial_seed=1)),
+    (4, 1, 0, dict(partial_steps=140, partial_seed=1)), (4, 1, 0, dict(partial_steps=210, partial_seed=1)),
+    (4, 1, 0, dict(partial_steps=280, partial_seed=1)),
 ]
 
 
@@ -108,7 +114,10 @@ def prebuild_kernels(kernels=DEFAULT_KERNELS, jobs: int = 8, verbose: bool = Tru
         n, mode, prec = k[:3]
         var = None
         if len(k) > 3:
-            var = QedVariant(**k[3])
+            kw = dict(k[3])
+            if "partial_steps" in kw:
+                kw["partial"] = 1
+            var = QedVariant(**kw)
         ms = ctypes.c_double(0.0)
         t = time.time()
         rc = lib.qed_prebuild(n, mode, prec, ctypes.byref(var) if var is not None else None, 1, ctypes.byref(ms))

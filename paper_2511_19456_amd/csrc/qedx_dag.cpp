@@ -250,11 +250,13 @@ Dag reduce_fixpoint(const Dag& d) {
   return r;
 }
 
-int64_t reduce_random_order(Dag& d, uint64_t seed) {
+int64_t reduce_random_order(Dag& d, uint64_t seed) { return reduce_steps(d, seed, -1); }
+
+int64_t reduce_steps(Dag& d, uint64_t seed, int64_t max_steps) {
   std::mt19937_64 rng(seed);
   std::vector<char> alive(d.nodes.size(), 1);
   int64_t steps = 0;
-  while (true) {
+  while (max_steps < 0 || steps < max_steps) {
     std::unordered_map<Key, std::vector<int32_t>, KeyHash> groups;
     for (size_t i = 0; i < d.nodes.size(); ++i) {
       if (!alive[i]) continue;

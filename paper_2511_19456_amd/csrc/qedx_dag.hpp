@@ -84,6 +84,11 @@ Dag reduce_fixpoint(const Dag& d);
 // One reduction at a time, groups picked in random order (for the
 // order-independence check).  Returns the number of reductions applied.
 int64_t reduce_random_order(Dag& d, uint64_t seed);
+// At most max_steps single reductions (all of them if max_steps < 0), in the
+// same seeded random order; the graph is compacted.  Returns the number
+// applied.  Partially reduced graphs are what the paper times against the
+// number of applied node reductions (Sec. III-D).
+int64_t reduce_steps(Dag& d, uint64_t seed, int64_t max_steps);
 
 // Rewrite S2(J, Jbar) = Jbar S(Q) J into Dot(J, S1(Jbar)) (join_side = 1) or
 // Dot(S1(J), Jbar) (join_side = 0).  Computationally equivalent (App. B-C).

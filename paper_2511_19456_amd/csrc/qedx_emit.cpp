@@ -34,6 +34,7 @@ std::string variant_tag(const Variant& v, int n_out, int n_in) {
     << v.lane_mask << "_o" << v.loop_mask << "_b" << v.block << "_s" << v.split << "_j" << v.join_side << "_r"
     << v.order << "_w" << v.min_waves;
   if (v.rewrite) o << "_d" << v.rewrite;
+  if (v.partial) o << "_k" << v.partial_steps << "s" << v.partial_seed;
   return o.str();
 }
 
@@ -42,6 +43,14 @@ Dag graph_for(const Process& proc, const Variant& v, double* t_build, double* t_
   auto t0 = clk::now();
   Dag d = build_unreduced(proc, v.enum_mask, v.split);
   auto t1 = clk::now();
+  if (v.partial) {
+    // the paper's form after the first partial_steps single node reductions
+    // (seeded random order), joins not split
+    reduce_steps(d, v.partial_seed, v.partial_steps);
+    if (t_build) *t_build = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (t_reduce) *t_reduce = std::chrono::duration<double, std::milli>(clk::now() - t1).count();
+    return d;
+  }
   Dag r = reduce_fixpoint(d);
   r = reduce_fixpoint(expand_joins(r, v.join_side));
   r = compact(r);
@@ -233,11 +242,20 @@ struct Emitter {
     auto ops = dot_ops(n);
     int sum = n.out.empty() ? -1 : d.nodes[n.out[0]].out[0];  // Dot -> Data -> Sum
     int acc = acc_of_sum.at(sum);
+    std::string B = name(ops.second);
+    if (n.kind == Kind::S2) {
+      // join of the paper's form (graphs that were not split): the row
+      // current is propagated here, Jbar S(Q) J
+      uint32_t mb = d.nodes[producer(ops.second)].mask;
+      emitQ(1, mb);
+      B = "qx::sR<" + T + ">(" + B + ", " + qname(1, mb) + ")";
+      st.flops_per_point += 56;
+    }
     if (v.prec == PREC_F64) {
-      os << ind << "qx::dot_acc<double>(A" << acc << ", " << name(ops.second) << ", " << name(ops.first) << ");\n";
+      os << ind << "qx::dot_acc<double>(A" << acc << ", " << B << ", " << name(ops.first) << ");\n";
       st.flops_per_point += 32;
     } else {
-      os << ind << "qx::comp_acc<float>(A" << acc << ", C" << acc << ", qx::dot<float>(" << name(ops.second) << ", "
+      os << ind << "qx::comp_acc<float>(A" << acc << ", C" << acc << ", qx::dot<float>(" << B << ", "
          << name(ops.first) << "));\n";
       st.flops_per_point += 30 + 14;
     }
@@ -257,7 +275,7 @@ struct Emitter {
   // share as many photons as possible.
   void partitions(std::map<uint32_t, std::vector<int>>& part, std::vector<uint32_t>& order) const {
     for (size_t i = 0; i < d.nodes.size(); ++i)
-      if (d.nodes[i].kind == Kind::Dot) {
+      if (d.nodes[i].kind == Kind::Dot || d.nodes[i].kind == Kind::S2) {
         auto ops = dot_ops(d.nodes[i]);
         part[d.nodes[producer(ops.first)].mask].push_back((int)i);
       }

@@ -27,6 +27,9 @@ struct Variant {
   int order = 0;        // emission order strategy (0 = partition-grouped)
   int min_waves = 0;    // __launch_bounds__ second argument (0 = none)
   int rewrite = 0;      // 0 = node reduction only; 1 = also the distributive rewrite
+  int partial = 0;      // 1: unsplit graph after partial_steps single reductions only
+  int partial_steps = 0;
+  uint32_t partial_seed = 0;
 };
 
 struct EmitStats {

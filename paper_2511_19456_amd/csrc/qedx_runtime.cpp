@@ -295,6 +295,16 @@ static qed_status make_variant(int n, qed_hel_mode mode, qed_precision prec, con
     if (qv->order) v.order = qv->order;
     if (qv->rewrite < 0 || qv->rewrite > 1) return fail(QED_ERR_INVALID_ARG, "rewrite must be 0 or 1");
     v.rewrite = qv->rewrite;
+    if (qv->partial) {
+      // partially reduced graph of the paper's form: whole graph in one
+      // straight-line block (the partition loop assumes identical partitions)
+      if (v.rewrite) return fail(QED_ERR_INVALID_ARG, "partial reduction excludes the rewrite");
+      if (qv->partial_steps < 0) return fail(QED_ERR_INVALID_ARG, "partial_steps must be >= 0");
+      v.partial = 1;
+      v.partial_steps = qv->partial_steps;
+      v.partial_seed = qv->partial_seed;
+      v.order = 0;
+    }
     if (mode == QED_HEL_SUM && (qv->lane_bits || qv->loop_bits)) {
       // both zero keeps the default helicity coverage
       uint32_t all = (1u << (n + 3)) - 1;
@@ -634,6 +644,23 @@ extern "C" qed_status qed_graph_interpret(int n, int n_in, uint32_t enum_mask, i
   Dag d = tool_graph(n, n_in, enum_mask, split, reduced);
   int np = n + n_in + 2;
   for (int64_t i = 0; i < N; ++i) out[i] = interpret(d, mom + 4 * np * i, hel ? hel[i] : 0u);
+  return QED_OK;
+}
+
+extern "C" qed_status qed_graph_partial(int n, int split, int64_t steps, uint64_t seed, const double* mom,
+                                        const uint32_t* hel, int64_t N, double* out, int64_t* counts) {
+  qed_status s = check_tool_args(n, 1, 0, split);
+  if (s) return s;
+  if (steps < 0 || N < 0 || (N > 0 && (!mom || !out))) return fail(QED_ERR_INVALID_ARG, "bad arguments");
+  Process pr = Process::make(n, 1);
+  Dag d = build_unreduced(pr, 0, split);
+  reduce_steps(d, seed, steps);
+  if (counts) {
+    Counts c = count(d);
+    int64_t v[10] = {c.total, c.data, c.compute, c.U, c.V, c.S1, c.S2, c.Dot, c.Sum, c.HelSum};
+    memcpy(counts, v, sizeof v);
+  }
+  for (int64_t i = 0; i < N; ++i) out[i] = interpret(d, mom + 4 * pr.npart * i, hel ? hel[i] : 0u);
   return QED_OK;
 }
 

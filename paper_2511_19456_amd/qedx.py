@@ -45,10 +45,15 @@ def _dev_tensor(t: torch.Tensor, dtype: torch.dtype, rows: int, name: str) -> to
 
 
 def make_variant(lane_bits: int = 0, loop_bits: int = 0, block: int = 0, split: int = 0,
-                 min_waves: int = 0, order: int = 0, rewrite: int = 0) -> QedVariant:
+                 min_waves: int = 0, order: int = 0, rewrite: int = 0,
+                 partial_steps: Optional[int] = None, partial_seed: int = 0) -> QedVariant:
     """Kernel shape (fields of qed_variant); rewrite=1 adds the distributive
-    rewrite after node reduction.  Zero fields take the library default."""
-    return QedVariant(lane_bits, loop_bits, block, split, min_waves, order, 0, rewrite)
+    rewrite after node reduction; partial_steps=k builds the paper's unsplit
+    graph after only k single node reductions (seeded random order).  Zero
+    fields take the library default."""
+    part = partial_steps is not None
+    return QedVariant(lane_bits, loop_bits, block, split, min_waves, order, 0, rewrite, int(part),
+                      int(partial_steps or 0), int(partial_seed))
 
 
 class QedProcess:
@@ -249,3 +254,21 @@ def emit_source(n: int, mode: str = "sum", precision: str = "fp64",
     buf = ctypes.create_string_buffer(ln.value + 1)
     check(lib().qed_emit_source(n, _MODES[mode], _PRECS[precision], vp, buf, ln.value + 1, ctypes.byref(ln)))
     return buf.value.decode()
+
+
+def graph_partial(n: int, steps: int, seed: int, mom_points=None, hel=None, split: Optional[int] = None):
+    """Counts (and, given points, interpreted |A|^2) of the unreduced graph after
+    `steps` single node reductions in the seeded random order."""
+    import numpy as np
+    split = split if split is not None else (n + 1) // 2
+    c = (ctypes.c_int64 * 10)()
+    if mom_points is None:
+        check(lib().qed_graph_partial(n, split, steps, seed, None, None, 0, None, c))
+        return dict(zip(COUNT_KEYS, list(c))), None
+    m = np.ascontiguousarray(np.asarray(mom_points, dtype=np.float64))
+    N = m.shape[0]
+    out = np.zeros(N, dtype=np.float64)
+    h = None if hel is None else np.ascontiguousarray(np.asarray(hel, dtype=np.uint32))
+    check(lib().qed_graph_partial(n, split, steps, seed, m.ctypes.data, None if h is None else h.ctypes.data, N,
+                                  out.ctypes.data, c))
+    return dict(zip(COUNT_KEYS, list(c))), out

@@ -188,3 +188,25 @@ def test_distributive_rewrite_lowers_compute_effort():
     c1r, _ = Q.graph_metrics(1, reduced=True, split=1)
     c1d, _ = Q.graph_metrics(1, reduced=2, split=1)
     assert c1r == c1d
+
+
+@pytest.mark.parametrize("steps", [0, 35, 140, 280])
+def test_partial_reduction_keeps_the_computation(steps):
+    """The reduction experiment's graphs (Sec. III-D): after any number of
+    single node reductions the graph computes the same amplitude (App. B-C);
+    0 steps is the unreduced graph of Table I and all 280 steps (n = 4, seed 1)
+    reach the fixpoint of the one-pass reduction."""
+    n, N = 4, 12
+    u, hel = inputs.rambo_inputs(29, n, N, with_helicities=True)
+    mom = O.momenta_from_uniforms(u, 15.0, n).numpy().reshape(N, -1)
+    c, got = Q.graph_partial(n, steps, 1, mom, hel)
+    ref = Q.graph_interpret(n, mom, hel, reduced=False)
+    tot = O.m2_sum(O.torch.as_tensor(mom.reshape(N, n + 3, 4)), O.Process(n)).numpy()
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * tot / (1 << (n + 3)))) < 1e-12
+    if steps == 0:
+        assert c["total"] == _table1()[n]
+    a, b, total = Q.reduction_check(n, 1, enum_mask=0, split=2)
+    assert total == 280
+    if steps == total:
+        fix = Q.graph_counts(n, split=2, reduced=False)
+        assert c["total"] < fix["total"] and c["S2"] == 120

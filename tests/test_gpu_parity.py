@@ -326,3 +326,21 @@ def test_distributive_rewrite_fp32c(n, mode, sqrt_s):
           f"median {np.median(err):.2e}")
     assert err.max() < 1e-4
     assert np.median(err) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# reduction experiment: partially reduced graphs of the paper's form
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("steps", [0, 140, 280])
+def test_partially_reduced_kernels(steps):
+    from paper_2511_19456_amd.qedx import make_variant
+    n, sqrt_s, N = 4, 15.0, 300
+    u, hel = inputs.rambo_inputs(33, n, N, with_helicities=True)
+    ref_mom = O.momenta_soa_from_uniforms(u, sqrt_s, n)
+    p = _proc(n, "per_point", "fp64", make_variant(partial_steps=steps, partial_seed=1))
+    assert p.info()["kernel_tag"].endswith(f"_k{steps}s1")
+    got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV),
+                 torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
+    ref = O.m2(ref_mom, n, "per_point", hel).numpy()
+    tot = O.m2(ref_mom, n, "sum").numpy()
+    assert (np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * tot / 128)).max() < 1e-10

@@ -225,6 +225,7 @@ Dag reduce_fixpoint(const Dag& d) {
   r.split = d.split;
   r.expanded = d.expanded;
   r.join_side = d.join_side;
+  r.distributed = d.distributed;
   std::vector<int32_t> rep(d.nodes.size(), -1);
   std::unordered_map<Key, int32_t, KeyHash> seen;
   seen.reserve(d.nodes.size());
@@ -335,6 +336,7 @@ Dag compact(const Dag& d) {
   r.split = d.split;
   r.expanded = d.expanded;
   r.join_side = d.join_side;
+  r.distributed = d.distributed;
   for (int32_t v : order) {
     Node m = d.nodes[v];
     for (auto& p : m.in) p = nid[p];
@@ -401,6 +403,7 @@ struct Distributor {
     r.split = d.split;
     r.expanded = d.expanded;
     r.join_side = d.join_side;
+  r.distributed = d.distributed;
     r.distributed = true;
   }
 

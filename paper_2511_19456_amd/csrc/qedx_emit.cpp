@@ -609,6 +609,158 @@ struct Emitter {
     os << ind << "}\n";
   }
 
+  // ---------------------------------------------------------------------
+  // Adjoint over a distributed graph (subset currents).  Its currents form a
+  // DAG (an Add has several parents), so the sweep runs top-down from each
+  // join: a node's adjoint is pushed to its inputs, recomputing the forward
+  // value of an input where a parameter gradient needs it.  Nothing but the
+  // adjoints of the current path is held.
+  // ---------------------------------------------------------------------
+  int tmpc = 0;
+  std::string tmpname(const char* p) { return std::string(p) + std::to_string(tmpc++); }
+
+  // statements computing the value of current node x; returns the variable
+  std::string fwd(int x) {
+    x = producer(x);
+    const Node& n = d.nodes[x];
+    std::string v = tmpname("f");
+    switch (n.kind) {
+      case Kind::U:
+        emit(x);
+        return name(x);
+      case Kind::V: {
+        std::string y = fwd(n.in[1]);
+        bool yp = d.nodes[producer(n.in[0])].hel == 1;
+        os << ind << "const qx::sp4<double> " << v << " = qx::v" << (n.side == 0 ? "L" : "R") << (yp ? "_y" : "")
+           << "<double>(" << y << ", " << name(n.in[0]) << ");\n";
+        st.flops_per_point += yp ? 24 : 40;
+        return v;
+      }
+      case Kind::S1: {
+        std::string y = fwd(n.in[0]);
+        os << ind << "qx::sp4<double> " << v << ";\n" << ind << "{\n";
+        std::string o = ind;
+        ind += "  ";
+        emit_K_inline(n.mask);
+        int pe = n.side == 0 ? pr.i_ein : pr.i_eout;
+        std::string m = "m" + std::to_string(pe) + "_";
+        os << ind << "const qx::propq<double> q = qx::prop_from<double>(" << m << "0, " << m << "1, " << m << "2, " << m
+           << "3, Kl0, Kl1, Kl2, Kl3, " << (n.side == 0 ? "1.0" : "-1.0") << ", 1.0);\n";
+        os << ind << v << " = qx::s" << (n.side == 0 ? "L" : "R") << "<double>(" << y << ", q);\n";
+        ind = o;
+        os << ind << "}\n";
+        st.flops_per_point += 28 + 56;
+        return v;
+      }
+      case Kind::Add: {
+        std::string e = fwd(n.in[0]);
+        for (size_t t = 1; t < n.in.size(); ++t) e = "qx::add4<double>(" + e + ", " + fwd(n.in[t]) + ")";
+        os << ind << "const qx::sp4<double> " << v << " = " << e << ";\n";
+        st.flops_per_point += 8.0 * (double)(n.in.size() - 1);
+        return v;
+      }
+      default:
+        throw std::logic_error("fwd(): not a current");
+    }
+  }
+
+  // push adjoint w of current node x to its inputs and to the momentum gradient
+  void adj(int x, const std::string& w) {
+    x = producer(x);
+    const Node& n = d.nodes[x];
+    switch (n.kind) {
+      case Kind::U:
+        if (n.particle == pr.i_eout) {
+          std::string m = "m" + std::to_string(pr.i_eout) + "_";
+          os << ind << "{ double g[4]; qx::ubar_vjp(" << m << "0, " << m << "1, " << m << "2, " << m << "3, "
+             << hel_expr(n) << ", 1.0, " << w << ", g);\n";
+          for (int mu = 0; mu < 4; ++mu) os << ind << "  " << gmref(pr.i_eout, mu) << " += g[" << mu << "];\n";
+          os << ind << "}\n";
+        }
+        return;
+      case Kind::Add:
+        for (int y : n.in) adj(y, w);
+        return;
+      case Kind::V: {
+        os << ind << "{\n";
+        std::string o = ind;
+        ind += "  ";
+        const std::string side = n.side == 0 ? "L" : "R", other = n.side == 0 ? "R" : "L";
+        std::string y = fwd(n.in[1]);
+        os << ind << "qx::v" << side << "_ge<double>(" << w << ", " << y << ", ge" << producer(n.in[0]) << ");\n";
+        std::string wy = tmpname("w");
+        os << ind << "const qx::sp4<double> " << wy << " = qx::v" << other << "<double>(" << w << ", "
+           << name(n.in[0]) << ");\n";
+        st.flops_per_point += 48 + 40;
+        adj(n.in[1], wy);
+        ind = o;
+        os << ind << "}\n";
+        return;
+      }
+      case Kind::S1: {
+        os << ind << "{\n";
+        std::string o = ind;
+        ind += "  ";
+        const std::string side = n.side == 0 ? "L" : "R", other = n.side == 0 ? "R" : "L";
+        std::string y = fwd(n.in[0]);
+        emit_K_inline(n.mask);
+        int pe = n.side == 0 ? pr.i_ein : pr.i_eout;
+        std::string m = "m" + std::to_string(pe) + "_";
+        os << ind << "const qx::propq<double> q = qx::prop_from<double>(" << m << "0, " << m << "1, " << m << "2, " << m
+           << "3, Kl0, Kl1, Kl2, Kl3, " << (n.side == 0 ? "1.0" : "-1.0") << ", 1.0);\n";
+        os << ind << "qx::propq<double> gq = {0.0, 0.0, 0.0, 0.0, 0.0};\n";
+        os << ind << "qx::s" << side << "_gq<double>(" << w << ", " << y << ", gq);\n";
+        prop_grad_to_momenta(n.side, n.mask);
+        std::string wy = tmpname("w");
+        os << ind << "const qx::sp4<double> " << wy << " = qx::s" << other << "<double>(" << w << ", q);\n";
+        st.flops_per_point += 28 + 64 + 60 + 56;
+        adj(n.in[0], wy);
+        ind = o;
+        os << ind << "}\n";
+        return;
+      }
+      default:
+        throw std::logic_error("adj(): not a current");
+    }
+  }
+
+  void dist_adjoint_block(uint32_t key, const std::vector<int>& dk) {
+    os << ind << "// adjoint (subset currents): photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << "\n";
+    std::string outer = open_block();
+    std::vector<int> pols;
+    for (size_t i = 0; i < d.nodes.size(); ++i) {
+      const Node& n = d.nodes[i];
+      if (n.kind == Kind::U && n.particle != pr.i_ein && n.particle != pr.i_eout) {
+        emit((int)i);
+        os << ind << "qx::pol3<double> ge" << i << " = {0.0, 0.0, 0.0};\n";
+        pols.push_back((int)i);
+      }
+    }
+    for (int k : dk) {
+      const Node& dn = d.nodes[k];
+      auto ops = dot_ops(dn);
+      int sum = d.nodes[dn.out[0]].out[0];
+      std::string jv = fwd(ops.first), bv = fwd(ops.second);
+      std::string wj = tmpname("w"), wb = tmpname("w");
+      os << ind << "qx::sp4<double> " << wj << " = qx::zero4<double>(), " << wb << " = qx::zero4<double>();\n";
+      os << ind << "qx::dot_vjp<double>(c" << acc_of_sum.at(sum) << ", " << bv << ", " << jv << ", " << wb << ", " << wj
+         << ");\n";
+      st.flops_per_point += 64;
+      adj(ops.second, wb);
+      adj(ops.first, wj);
+    }
+    for (int u : pols) {
+      const Node& n = d.nodes[u];
+      if (!final_particle(n.particle)) continue;
+      std::string m = "m" + std::to_string(n.particle) + "_";
+      os << ind << "{ double g[3]; qx::pol_vjp(" << m << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", ge" << u
+         << ", g);\n";
+      for (int mu = 1; mu < 4; ++mu) os << ind << "  " << gmref(n.particle, mu) << " += g[" << (mu - 1) << "];\n";
+      os << ind << "}\n";
+    }
+    close_block(outer);
+  }
+
   void grad_block(uint32_t key, const std::vector<int>& dk) {
     collect_block(dk);
     os << ind << "// adjoint: photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << "\n";
@@ -919,8 +1071,10 @@ std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& k
 std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const std::string& kprefix, int* count,
                                            EmitStats* stats) {
   check_variant(d, v);
-  if (v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4) || (v.order & (8 | 16)) || d.distributed)
-    throw std::invalid_argument("adjoint kernels take SUM, FP64, local blocks, the node-reduced graph");
+  if (v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4) || (v.order & (8 | 16)))
+    throw std::invalid_argument("adjoint kernels take SUM, FP64, local blocks");
+  if (d.distributed && v.enum_mask)
+    throw std::invalid_argument("adjoint kernels of the distributed graph take one configuration per iteration");
   const Process& pr = d.proc;
   const int LB = popc(v.lane_mask), G = 1 << LB;
   const int nloop = popc(v.loop_mask);
@@ -961,7 +1115,10 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
       os << e.ind << "const qx::cx<double> c" << a << " = {amp[(2 * h" << a << ") * N + ptc] * iM2, -amp[(2 * h" << a
          << " + 1) * N + ptc] * iM2};\n";
     }
-    e.grad_block(key, part[key]);
+    if (d.distributed)
+      e.dist_adjoint_block(key, part[key]);
+    else
+      e.grad_block(key, part[key]);
     e.ind = "  ";
     os << "  }\n";
     for (int p = 2; p < pr.npart; ++p)

@@ -332,8 +332,9 @@ static std::string eval_kernel_name(int n, qed_hel_mode mode, qed_precision prec
 
 // The auxiliary module (RAMBO, gradient) depends on the process, mode and
 // precision only, not on the eval kernel's shape: one cache entry per process.
-static std::string aux_tag(int n, qed_hel_mode mode, qed_precision prec) {
-  return "aux_n" + std::to_string(n) + (mode == QED_HEL_SUM ? "_sum" : "_pp") + (prec == QED_FP64 ? "_fp64" : "_fp32c");
+static std::string aux_tag(int n, qed_hel_mode mode, qed_precision prec, int rewrite) {
+  return "aux_n" + std::to_string(n) + (mode == QED_HEL_SUM ? "_sum" : "_pp") + (prec == QED_FP64 ? "_fp64" : "_fp32c") +
+         (rewrite ? "_d" + std::to_string(rewrite) : "");
 }
 
 static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* qv, Variant& v,
@@ -415,7 +416,7 @@ extern "C" qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec,
     } catch (const std::exception& e) {
       return fail(QED_ERR_INVALID_ARG, std::string("aux emit: ") + e.what());
     }
-    std::string atag = aux_tag(n, mode, prec);
+    std::string atag = aux_tag(n, mode, prec, v.rewrite);
     s = get_code_object(atag, asrc, co, meta, hit, ms2);
     if (s) return s;
   }
@@ -469,7 +470,7 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   KernelMeta am;
   bool ahit;
   double ams;
-  s = get_code_object(aux_tag(n, mode, prec), asrc, aco, am, ahit, ams);
+  s = get_code_object(aux_tag(n, mode, prec, p->var.rewrite), asrc, aco, am, ahit, ams);
   if (s) return s;
   p->info.create_ms_compile += ams;
   HIPCHK(hipModuleLoadData(&p->mod_aux, aco.data()));

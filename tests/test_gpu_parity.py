@@ -157,10 +157,12 @@ def test_fp32c_error_bound(n, mode, sqrt_s):
 # ---------------------------------------------------------------------------
 # gradient of log|M|^2 through RAMBO (adjoint kernel)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("n,sqrt_s,N", [(1, 4.0, 200), (2, 6.0, 200), (3, 10.0, 128), (4, 15.0, 96)])
-def test_gradient_vs_oracle(n, sqrt_s, N):
+@pytest.mark.parametrize("n,sqrt_s,N,rewrite", [(1, 4.0, 200, 0), (2, 6.0, 200, 0), (3, 10.0, 128, 0),
+                                                 (4, 15.0, 96, 0), (4, 15.0, 96, 1)])
+def test_gradient_vs_oracle(n, sqrt_s, N, rewrite):
+    from paper_2511_19456_amd.qedx import make_variant
     u, _ = inputs.rambo_inputs(5, n, N)
-    p = _proc(n, "sum")
+    p = _proc(n, "sum", "fp64", make_variant(rewrite=1) if rewrite else None)
     val, g = p.eval_grad(torch.as_tensor(u, device=DEV), sqrt_s)
     v_o, g_o = O.logm2_and_grad(u, sqrt_s, n)
     assert np.abs(val.cpu().numpy() - v_o.numpy()).max() < 1e-10 * max(1.0, np.abs(v_o.numpy()).max())

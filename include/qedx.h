@@ -109,7 +109,7 @@ typedef struct {
   int32_t cache_hit;         /* 1 if the code object came from the cache */
   char kernel_tag[160];      /* kernel shape: process, mode, precision, helicity coverage, schedule */
   char code_hash[24];        /* hash of the eval kernel's source, flags and target (changes with the code) */
-  char kernel_name[48];      /* symbol of the eval kernel, qedx_eval_n<n>_<sum|pp>_<fp64|fp32c>[_d1] */
+  char kernel_name[48];      /* symbol of the eval kernel, qedx_eval_n<n>_<sum|pp>_<fp64|fp32c>[_d1][_k<steps>] */
 } qed_info;
 
 /* Build the graph for n outgoing photons (1..6), reduce it, emit and compile

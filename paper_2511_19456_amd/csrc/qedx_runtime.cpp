@@ -323,10 +323,11 @@ static qed_status make_variant(int n, qed_hel_mode mode, qed_precision prec, con
 
 // Symbol of the eval kernel: one name per (process, mode, precision, rewrite),
 // so profiles tell the kernels of different processes apart.
-static std::string eval_kernel_name(int n, qed_hel_mode mode, qed_precision prec, int rewrite) {
+static std::string eval_kernel_name(int n, qed_hel_mode mode, qed_precision prec, const Variant& v) {
   std::string k = "qedx_eval_n" + std::to_string(n) + (mode == QED_HEL_SUM ? "_sum" : "_pp") +
                   (prec == QED_FP64 ? "_fp64" : "_fp32c");
-  if (rewrite) k += "_d" + std::to_string(rewrite);
+  if (v.rewrite) k += "_d" + std::to_string(v.rewrite);
+  if (v.partial) k += "_k" + std::to_string(v.partial_steps);
   return k;
 }
 
@@ -356,7 +357,7 @@ static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, con
     info.nodes_reduced = (int64_t)d.nodes.size();
     auto t0 = std::chrono::steady_clock::now();
     EmitStats st;
-    src = emit_eval_kernel(d, v, eval_kernel_name(n, mode, prec, v.rewrite), &st);
+    src = emit_eval_kernel(d, v, eval_kernel_name(n, mode, prec, v), &st);
     info.create_ms_emit = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     info.n_V = st.n_V;
     info.n_S1 = st.n_S1;
@@ -373,7 +374,7 @@ static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, con
   info.block = v.block;
   std::string tag = variant_tag(v, n, 1);
   snprintf(info.kernel_tag, sizeof info.kernel_tag, "%s", tag.c_str());
-  snprintf(info.kernel_name, sizeof info.kernel_name, "%s", eval_kernel_name(n, mode, prec, v.rewrite).c_str());
+  snprintf(info.kernel_name, sizeof info.kernel_name, "%s", eval_kernel_name(n, mode, prec, v).c_str());
   return QED_OK;
 }
 

@@ -316,6 +316,37 @@ def extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom_n3):
                 r["max_rel_diff_vs_plain"] = err
             return r
         return run
+    def mixed_small():
+        """Many small segments (48 segments, n cycling 1..6, N log-uniform in
+        [10^3, 10^4]): the regime where one persistent graph launch replaces
+        many short kernel launches."""
+        from paper_2511_19456_amd.qedx import BatchPlan
+        g = inputs.rng_for(41)
+        procs = {n: QedProcess(n, "per_point", "fp64") for n in range(1, 7)}
+        segs, tot_flops, tot_pts = [], 0.0, 0
+        for i in range(48):
+            n = 1 + i % 6
+            Np = int(round(10.0 ** g.uniform(3.0, 4.0)))
+            rs = float(g.uniform(5.0, 30.0))
+            u, h = inputs.rambo_inputs(2000 + i, n, Np, with_helicities=True)
+            p = procs[n]
+            m = p.rambo(torch.as_tensor(u, device=dev), rs)
+            segs.append((p, m, torch.as_tensor(h.astype(np.int32), device=dev),
+                         torch.empty(Np, dtype=torch.float64, device=dev)))
+            tot_flops += alg_flops(n, "per_point") * Np
+            tot_pts += Np
+        torch.cuda.synchronize()
+        plan = BatchPlan(segs, tile_points=0)
+        ms_b = time_launches(plan.launch, steps, 2)
+
+        def plain():
+            for p, m, hd, o in segs:
+                p.eval(m, hd, out=o)
+        ms_p = time_launches(plain, steps, 2)
+        return {"segments": len(segs), "points": tot_pts, "ms": ms_b, "points_per_s": tot_pts / (ms_b * 1e-3),
+                "alg_tflops": tot_flops / (ms_b * 1e-3) / 1e12, "plan": plan.info(),
+                "ms_plain_launches": ms_p, "speedup_vs_plain_fp64": ms_p / ms_b}
+    _leg(legs, "mixed_small_48seg_fp64", want, mixed_small)
     _leg(legs, "mixed_n1to6_fp64", want, mixed("fp64"))
     _leg(legs, "mixed_n1to6_fp32c", want, mixed("fp32c"))
 

@@ -109,7 +109,8 @@ typedef struct {
   int32_t cache_hit;         /* 1 if the code object came from the cache */
   char kernel_tag[160];      /* kernel shape: process, mode, precision, helicity coverage, schedule */
   char code_hash[24];        /* hash of the eval kernel's source, flags and target (changes with the code) */
-  char kernel_name[48];      /* symbol of the eval kernel, qedx_eval_n<n>_<sum|pp>_<fp64|fp32c>[_d1][_k<steps>] */
+  char kernel_name[48];      /* symbol of the eval kernel, qedx_eval_[i<n_in>]n<n>_<sum|pp>_<fp64|fp32c>[_d1][_k<steps>] */
+  int32_t n_in;              /* incoming photons (1 unless created by qed_process_create_crossed) */
 } qed_info;
 
 /* Build the graph for n outgoing photons (1..6), reduce it, emit and compile
@@ -119,6 +120,16 @@ typedef struct {
  * or a mode/precision not built for that n. */
 qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
                               qed_process** out);
+/* The crossed process e-(p) + n_in photons -> e-(p') + n_out photons on one
+ * electron line (n_in, n_out >= 1, n_in + n_out <= 7), e.g. the paper's Table I
+ * processes e- gamma^n -> e- gamma (n_out = 1).  Same (n_in + n_out)! diagrams
+ * and graph; particle order [e-_in, gamma_in_1..n_in, e-_out, gamma_out_1..n_out],
+ * so momenta are [4(n_in + n_out + 2)][N] and helicity bit i belongs to
+ * particle i.  Incoming photons carry eps, outgoing eps* (equal: real linear
+ * polarisations).  qed_eval and batches work as for one incoming photon;
+ * qed_rambo and qed_eval_grad return UNSUPPORTED for n_in > 1. */
+qed_status qed_process_create_crossed(int n_in, int n_out, qed_hel_mode mode, qed_precision prec,
+                                      const qed_variant* variant, qed_process** out);
 qed_status qed_process_destroy(qed_process* p);
 qed_status qed_process_info(const qed_process* p, qed_info* out);
 
@@ -233,6 +244,10 @@ qed_status qed_graph_metrics(int n, int n_in, uint32_t enum_mask, int split, int
  * (0 on a cache hit). */
 qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant, int with_aux,
                         double* compile_ms);
+/* The same for the eval kernel of a crossed process (qed_process_create_crossed
+ * arguments); there is no auxiliary module for n_in > 1. */
+qed_status qed_prebuild_crossed(int n_in, int n_out, qed_hel_mode mode, qed_precision prec,
+                                const qed_variant* variant, double* compile_ms);
 
 /* Host references of the gradient pieces (no GPU), for tests:
  * qed_graph_grad_interpret: F = log(sum over all configurations of |A|^2) and

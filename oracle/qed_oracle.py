@@ -265,10 +265,11 @@ def points_to_soa(mom: torch.Tensor) -> torch.Tensor:
     return mom.permute(1, 2, 0).reshape(4 * npart, N).contiguous()
 
 
-def m2(m_soa, n: int, mode: str, hel=None, chunk: int = 2048) -> torch.Tensor:
-    """|M|^2 in reduced units for SoA momenta ``[4(n+3)][N]``; mode 'sum' or 'per_point'."""
+def m2(m_soa, n: int, mode: str, hel=None, chunk: int = 2048, n_in: int = 1) -> torch.Tensor:
+    """|M|^2 in reduced units for SoA momenta ``[4(n+n_in+2)][N]`` of
+    e- gamma^n_in -> e- gamma^n; mode 'sum' or 'per_point'."""
     mom = soa_to_points(m_soa)
-    proc = Process(n)
+    proc = Process(n, n_in=n_in)
     outs = []
     for s in range(0, mom.shape[0], chunk):
         mm = mom[s:s + chunk]

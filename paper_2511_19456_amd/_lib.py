@@ -41,7 +41,7 @@ class QedInfo(ctypes.Structure):
                 ("create_ms_build", c_double), ("create_ms_reduce", c_double), ("create_ms_emit", c_double),
                 ("create_ms_compile", c_double), ("create_ms_load", c_double),
                 ("cache_hit", ctypes.c_int32), ("kernel_tag", ctypes.c_char * 160),
-                ("code_hash", ctypes.c_char * 24), ("kernel_name", ctypes.c_char * 48)]
+                ("code_hash", ctypes.c_char * 24), ("kernel_name", ctypes.c_char * 48), ("n_in", ctypes.c_int32)]
 
 
 class QedSegment(ctypes.Structure):
@@ -51,6 +51,8 @@ class QedSegment(ctypes.Structure):
 # exported symbol -> (restype, argtypes); the header declares every one
 SIGNATURES = {
     "qed_process_create": (c_int, [c_int, c_int, c_int, ctypes.POINTER(QedVariant), ctypes.POINTER(c_void_p)]),
+    "qed_process_create_crossed": (c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(QedVariant),
+                                           ctypes.POINTER(c_void_p)]),
     "qed_process_destroy": (c_int, [c_void_p]),
     "qed_process_info": (c_int, [c_void_p, ctypes.POINTER(QedInfo)]),
     "qed_eval": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
@@ -72,6 +74,8 @@ SIGNATURES = {
                                 ctypes.POINTER(c_int64)]),
     "qed_prebuild": (c_int, [c_int, c_int, c_int, ctypes.POINTER(QedVariant), c_int,
                              ctypes.POINTER(c_double)]),
+    "qed_prebuild_crossed": (c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(QedVariant),
+                                     ctypes.POINTER(c_double)]),
     "qed_graph_grad_interpret": (c_int, [c_int, c_int, c_int, c_void_p, c_int64, c_void_p, c_void_p]),
     "qed_rambo_vjp_host": (c_int, [c_int, c_void_p, c_double, c_void_p, c_int64, c_void_p, c_void_p]),
     "qed_graph_partial": (c_int, [c_int, c_int, c_int64, ctypes.c_uint64, c_void_p, c_void_p, c_int64, c_void_p,

@@ -100,6 +100,11 @@ DEFAULT_KERNELS = [
     (4, 1, 0, dict(partial_steps=0, partial_seed=1)), (4, 1, 0, dict(partial_steps=70, partial_seed=1)),
     (4, 1, 0, dict(partial_steps=140, partial_seed=1)), (4, 1, 0, dict(partial_steps=210, partial_seed=1)),
     (4, 1, 0, dict(partial_steps=280, partial_seed=1)),
+    # Table I orientation e- gamma^n_in -> e- gamma (crossed processes, eval kernel only)
+    (1, 0, 0, dict(n_in=2)), (1, 0, 0, dict(n_in=3)), (1, 0, 0, dict(n_in=4)), (1, 0, 1, dict(n_in=3)),
+    (1, 1, 0, dict(n_in=2)), (1, 1, 0, dict(n_in=3)), (1, 1, 0, dict(n_in=4)), (1, 1, 0, dict(n_in=5)),
+    (1, 1, 0, dict(n_in=6)), (1, 1, 1, dict(n_in=3)), (1, 1, 1, dict(n_in=6)), (2, 0, 0, dict(n_in=2)),
+    (1, 1, 0, dict(n_in=6, rewrite=1)),
 ]
 
 
@@ -108,19 +113,28 @@ def prebuild_kernels(kernels=DEFAULT_KERNELS, jobs: int = 8, verbose: bool = Tru
     lib.qed_prebuild.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_double)]
     lib.qed_prebuild.restype = ctypes.c_int
+    lib.qed_prebuild_crossed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_double)]
+    lib.qed_prebuild_crossed.restype = ctypes.c_int
     lib.qed_last_error.restype = ctypes.c_char_p
 
     def one(k):
         n, mode, prec = k[:3]
         var = None
+        n_in = 1
         if len(k) > 3:
             kw = dict(k[3])
+            n_in = kw.pop("n_in", 1)
             if "partial_steps" in kw:
                 kw["partial"] = 1
-            var = QedVariant(**kw)
+            var = QedVariant(**kw) if kw else None
         ms = ctypes.c_double(0.0)
         t = time.time()
-        rc = lib.qed_prebuild(n, mode, prec, ctypes.byref(var) if var is not None else None, 1, ctypes.byref(ms))
+        vp = ctypes.byref(var) if var is not None else None
+        if n_in == 1:
+            rc = lib.qed_prebuild(n, mode, prec, vp, 1, ctypes.byref(ms))
+        else:
+            rc = lib.qed_prebuild_crossed(n_in, n, mode, prec, vp, ctypes.byref(ms))
         err = lib.qed_last_error().decode() if rc else ""
         return k, rc, ms.value, time.time() - t, err
 

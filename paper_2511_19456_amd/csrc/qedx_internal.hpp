@@ -17,7 +17,8 @@ struct KernelMeta {
 };
 
 struct qed_process {
-  int n = 0;
+  int n = 0;     // outgoing photons
+  int n_in = 1;  // incoming photons
   qed_hel_mode mode = QED_HEL_SUM;
   qed_precision prec = QED_FP64;
   qedx::Variant var;

@@ -249,33 +249,33 @@ static qed_status get_code_object(const std::string& tag, const std::string& src
 // processes
 // ---------------------------------------------------------------------------
 
-static void default_variant(int n, qed_hel_mode mode, qed_precision prec, Variant& v) {
+static void default_variant(int n, int nin, qed_hel_mode mode, qed_precision prec, Variant& v) {
   v = Variant();
   v.prec = prec == QED_FP64 ? PREC_F64 : PREC_F32C;
   v.mode = mode == QED_HEL_SUM ? HEL_SUM : HEL_PER_POINT;
-  int P = n + 1;
+  const int P = n + nin, npart = P + 2, i_eout = 1 + nin;
   v.split = P / 2;
   v.block = 256;
   v.join_side = 1;
-  // n <= 3: one shared graph per lane (few partitions, registers suffice).
-  // n >= 4: per photon partition, its currents recomputed (bounded live set):
-  // helicity sums use one basic block per partition; per-point kernels a
-  // run-time loop over the partitions around one canonical block (compact
-  // code, seconds to compile even at n = 6).
-  v.order = n >= 4 ? (mode == QED_HEL_PER_POINT ? 8 : 4) : 0;
+  // P <= 4 photons: one shared graph per lane (few partitions, registers
+  // suffice).  P >= 5: per photon partition, its currents recomputed
+  // (bounded live set): helicity sums use one basic block per partition;
+  // per-point kernels a run-time loop over the partitions around one
+  // canonical block (compact code, seconds to compile even at P = 7).
+  v.order = P >= 5 ? (mode == QED_HEL_PER_POINT ? 8 : 4) : 0;
   if (mode == QED_HEL_SUM) {
-    uint32_t all = (1u << (n + 3)) - 1;
+    uint32_t all = (1u << npart) - 1;
     // electron spins over lanes; photon polarisations shared in the graph
-    // for small n, partly looped for larger n
-    v.lane_mask = (1u << 0) | (1u << 2);
+    // for few photons, partly looped for more
+    v.lane_mask = (1u << 0) | (1u << i_eout);
     uint32_t photons = all & ~v.lane_mask;
-    if (n <= 3) {
+    if (P <= 4) {
       v.enum_mask = photons;
     } else {
       // keep 2^3 configurations inside the graph, loop over the rest
       uint32_t e = 0;
       int k = 0;
-      for (int b = 0; b < n + 3 && k < 3; ++b)
+      for (int b = 0; b < npart && k < 3; ++b)
         if ((photons >> b) & 1) {
           e |= 1u << b;
           ++k;
@@ -286,8 +286,10 @@ static void default_variant(int n, qed_hel_mode mode, qed_precision prec, Varian
   }
 }
 
-static qed_status make_variant(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* qv, Variant& v) {
-  default_variant(n, mode, prec, v);
+static qed_status make_variant(int n, int nin, qed_hel_mode mode, qed_precision prec, const qed_variant* qv,
+                               Variant& v) {
+  default_variant(n, nin, mode, prec, v);
+  const int P = n + nin, npart = P + 2;
   if (qv && !qv->use_defaults) {
     if (qv->block) v.block = qv->block;
     if (qv->split) v.split = qv->split;
@@ -307,7 +309,7 @@ static qed_status make_variant(int n, qed_hel_mode mode, qed_precision prec, con
     }
     if (mode == QED_HEL_SUM && (qv->lane_bits || qv->loop_bits)) {
       // both zero keeps the default helicity coverage
-      uint32_t all = (1u << (n + 3)) - 1;
+      uint32_t all = (1u << npart) - 1;
       v.lane_mask = qv->lane_bits & all;
       v.loop_mask = qv->loop_bits & all & ~v.lane_mask;
       v.enum_mask = all & ~v.lane_mask & ~v.loop_mask;
@@ -316,16 +318,16 @@ static qed_status make_variant(int n, qed_hel_mode mode, qed_precision prec, con
     }
   }
   if (v.block % 64 || v.block < 64 || v.block > 1024) return fail(QED_ERR_INVALID_ARG, "block must be 64..1024, multiple of 64");
-  if (v.split < 1 || v.split > n) return fail(QED_ERR_INVALID_ARG, "split must be in 1..n");
+  if (v.split < 1 || v.split > P - 1) return fail(QED_ERR_INVALID_ARG, "split must be in 1..(photons - 1)");
   if (__builtin_popcount(v.lane_mask) > 6) return fail(QED_ERR_INVALID_ARG, "at most 6 lane bits");
   return QED_OK;
 }
 
 // Symbol of the eval kernel: one name per (process, mode, precision, rewrite),
 // so profiles tell the kernels of different processes apart.
-static std::string eval_kernel_name(int n, qed_hel_mode mode, qed_precision prec, const Variant& v) {
-  std::string k = "qedx_eval_n" + std::to_string(n) + (mode == QED_HEL_SUM ? "_sum" : "_pp") +
-                  (prec == QED_FP64 ? "_fp64" : "_fp32c");
+static std::string eval_kernel_name(int n, int nin, qed_hel_mode mode, qed_precision prec, const Variant& v) {
+  std::string k = "qedx_eval_" + (nin != 1 ? "i" + std::to_string(nin) : std::string()) + "n" + std::to_string(n) +
+                  (mode == QED_HEL_SUM ? "_sum" : "_pp") + (prec == QED_FP64 ? "_fp64" : "_fp32c");
   if (v.rewrite) k += "_d" + std::to_string(v.rewrite);
   if (v.partial) k += "_k" + std::to_string(v.partial_steps);
   return k;
@@ -338,14 +340,14 @@ static std::string aux_tag(int n, qed_hel_mode mode, qed_precision prec, int rew
          (rewrite ? "_d" + std::to_string(rewrite) : "");
 }
 
-static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* qv, Variant& v,
-                               Process& proc, std::string& src, qed_info& info) {
-  if (n < 1 || n > 6) return fail(QED_ERR_UNSUPPORTED, "n must be in 1..6");
+static qed_status build_source(int n, int nin, qed_hel_mode mode, qed_precision prec, const qed_variant* qv,
+                               Variant& v, Process& proc, std::string& src, qed_info& info) {
+  if (n < 1 || nin < 1 || n + nin > 7) return fail(QED_ERR_UNSUPPORTED, "need n_out >= 1, n_in >= 1, n_in + n_out <= 7");
   if (mode != QED_HEL_SUM && mode != QED_HEL_PER_POINT) return fail(QED_ERR_INVALID_ARG, "bad helicity mode");
   if (prec != QED_FP64 && prec != QED_FP32C) return fail(QED_ERR_INVALID_ARG, "bad precision");
-  qed_status s = make_variant(n, mode, prec, qv, v);
+  qed_status s = make_variant(n, nin, mode, prec, qv, v);
   if (s) return s;
-  proc = Process::make(n, 1);
+  proc = Process::make(n, nin);
   try {
     double tb = 0, tr = 0;
     Dag un = build_unreduced(proc, v.enum_mask, v.split);
@@ -357,7 +359,7 @@ static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, con
     info.nodes_reduced = (int64_t)d.nodes.size();
     auto t0 = std::chrono::steady_clock::now();
     EmitStats st;
-    src = emit_eval_kernel(d, v, eval_kernel_name(n, mode, prec, v), &st);
+    src = emit_eval_kernel(d, v, eval_kernel_name(n, nin, mode, prec, v), &st);
     info.create_ms_emit = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     info.n_V = st.n_V;
     info.n_S1 = st.n_S1;
@@ -372,9 +374,10 @@ static qed_status build_source(int n, qed_hel_mode mode, qed_precision prec, con
   info.precision = prec;
   info.lanes_per_point = 1 << __builtin_popcount(v.lane_mask);
   info.block = v.block;
-  std::string tag = variant_tag(v, n, 1);
+  std::string tag = variant_tag(v, n, nin);
   snprintf(info.kernel_tag, sizeof info.kernel_tag, "%s", tag.c_str());
-  snprintf(info.kernel_name, sizeof info.kernel_name, "%s", eval_kernel_name(n, mode, prec, v).c_str());
+  snprintf(info.kernel_name, sizeof info.kernel_name, "%s", eval_kernel_name(n, nin, mode, prec, v).c_str());
+  info.n_in = nin;
   return QED_OK;
 }
 
@@ -384,7 +387,7 @@ extern "C" qed_status qed_emit_source(int n, qed_hel_mode mode, qed_precision pr
   Process proc;
   std::string src;
   qed_info info{};
-  qed_status s = build_source(n, mode, prec, variant, v, proc, src, info);
+  qed_status s = build_source(n, 1, mode, prec, variant, v, proc, src, info);
   if (s) return s;
   if (len) *len = (int64_t)src.size();
   if (buf && buflen > 0) {
@@ -396,13 +399,13 @@ extern "C" qed_status qed_emit_source(int n, qed_hel_mode mode, qed_precision pr
 }
 
 // Emit + compile into the cache without touching the GPU (used to prebuild).
-extern "C" qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
-                                   int with_aux, double* compile_ms) {
+static qed_status prebuild(int nin, int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
+                           int with_aux, double* compile_ms) {
   Variant v;
   Process proc;
   std::string src;
   qed_info info{};
-  qed_status s = build_source(n, mode, prec, variant, v, proc, src, info);
+  qed_status s = build_source(n, nin, mode, prec, variant, v, proc, src, info);
   if (s) return s;
   std::string co;
   KernelMeta meta;
@@ -410,7 +413,7 @@ extern "C" qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec,
   double ms = 0, ms2 = 0;
   s = get_code_object(info.kernel_tag, src, co, meta, hit, ms);
   if (s) return s;
-  if (with_aux) {
+  if (with_aux && nin == 1) {
     std::string asrc;
     try {
       asrc = emit_aux_module(proc, v, n, nullptr);
@@ -425,14 +428,25 @@ extern "C" qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec,
   return QED_OK;
 }
 
-extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
-                                         qed_process** out) {
+extern "C" qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
+                                   int with_aux, double* compile_ms) {
+  return prebuild(1, n, mode, prec, variant, with_aux, compile_ms);
+}
+
+extern "C" qed_status qed_prebuild_crossed(int n_in, int n_out, qed_hel_mode mode, qed_precision prec,
+                                           const qed_variant* variant, double* compile_ms) {
+  return prebuild(n_in, n_out, mode, prec, variant, 0, compile_ms);
+}
+
+static qed_status process_create(int nin, int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
+                                 qed_process** out) {
   if (!out) return fail(QED_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   auto p = std::make_unique<qed_process>();
-  qed_status s = build_source(n, mode, prec, variant, p->var, p->proc, p->eval_src, p->info);
+  qed_status s = build_source(n, nin, mode, prec, variant, p->var, p->proc, p->eval_src, p->info);
   if (s) return s;
   p->n = n;
+  p->n_in = nin;
   p->mode = mode;
   p->prec = prec;
   p->lanes = p->info.lanes_per_point;
@@ -453,6 +467,11 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   auto t0 = std::chrono::steady_clock::now();
   HIPCHK(hipModuleLoadData(&p->mod, co.data()));
   HIPCHK(hipModuleGetFunction(&p->f_eval, p->mod, p->info.kernel_name));
+  if (nin != 1) {  // RAMBO and the gradient are built for one incoming photon
+    p->info.create_ms_load = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = p.release();
+    return QED_OK;
+  }
   // auxiliary module: RAMBO (all processes) and the gradient kernel
   std::string asrc;
   try {
@@ -491,6 +510,16 @@ extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision
   return QED_OK;
 }
 
+extern "C" qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant,
+                                         qed_process** out) {
+  return process_create(1, n, mode, prec, variant, out);
+}
+
+extern "C" qed_status qed_process_create_crossed(int n_in, int n_out, qed_hel_mode mode, qed_precision prec,
+                                                 const qed_variant* variant, qed_process** out) {
+  return process_create(n_in, n_out, mode, prec, variant, out);
+}
+
 extern "C" qed_status qed_process_destroy(qed_process* p) {
   delete p;  // unloads its modules
   return QED_OK;
@@ -527,6 +556,7 @@ extern "C" qed_status qed_eval(const qed_process* p, const double* momenta, cons
 extern "C" qed_status qed_rambo(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N,
                                 double* momenta_out, void* stream) {
   if (!p) return fail(QED_ERR_INVALID_ARG, "process is NULL");
+  if (!p->f_rambo) return fail(QED_ERR_UNSUPPORTED, "RAMBO is built for one incoming photon");
   if (N < 0) return fail(QED_ERR_INVALID_ARG, "N < 0");
   if (!(sqrt_s > 1.0) || !std::isfinite(sqrt_s)) return fail(QED_ERR_INVALID_ARG, "sqrt_s must exceed m = 1");
   if (N == 0) return QED_OK;
@@ -540,8 +570,8 @@ extern "C" qed_status qed_eval_grad(const qed_process* p, const double* uniforms
                                     const uint32_t* hel, int64_t N, double* out_logm2, double* out_grad,
                                     void* stream) {
   if (!p) return fail(QED_ERR_INVALID_ARG, "process is NULL");
-  if (p->mode != QED_HEL_SUM || p->prec != QED_FP64)
-    return fail(QED_ERR_UNSUPPORTED, "gradient is built for SUM-mode FP64 processes");
+  if (p->mode != QED_HEL_SUM || p->prec != QED_FP64 || p->n_in != 1)
+    return fail(QED_ERR_UNSUPPORTED, "gradient is built for SUM-mode FP64 processes with one incoming photon");
   if (hel) return fail(QED_ERR_INVALID_ARG, "hel must be NULL");
   if (N < 0) return fail(QED_ERR_INVALID_ARG, "N < 0");
   if (!(sqrt_s > 1.0) || !std::isfinite(sqrt_s)) return fail(QED_ERR_INVALID_ARG, "sqrt_s must exceed m = 1");
@@ -555,7 +585,7 @@ extern "C" qed_status qed_eval_grad(const qed_process* p, const double* uniforms
   }
   // Split gradient over chunks of C points.  Workspace per point: momenta and
   // momentum gradient [4(n+3)] each, amplitudes [2 * 2^(n+3)], 1/|M|^2.
-  const int npart = p->n + 3;
+  const int npart = p->n + p->n_in + 2;
   const int64_t H = (int64_t)1 << npart;
   const int64_t per_pt = 8 * (2 * 4 * (int64_t)npart + 2 * H + 1);
   int64_t C = (int64_t)1 << 20;
@@ -710,6 +740,6 @@ qed_status get_code_object(const std::string& tag, const std::string& src, std::
 }
 std::string cache_dir() { return cache_dir_str(); }
 qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, qedx::Variant& v) {
-  return make_variant(n, mode, prec, nullptr, v);
+  return make_variant(n, 1, mode, prec, nullptr, v);
 }
 }  // namespace qedx_rt

@@ -18,6 +18,9 @@ Generators
   cos(theta) ~ U(-1,1), phi ~ U(0, 2 pi).  The outgoing photon energy follows
   from two-body kinematics, and the outgoing electron from momentum
   conservation.  Returned SoA ``[16][N]`` (row = 4 * particle + mu).
+* ``crossed_inputs(seed, n_in, N)``: e- gamma^n_in -> e- gamma, electron at
+  rest, incoming photons with random energies and directions, the outgoing
+  photon isotropic in the centre-of-mass frame (two-body kinematics).
 * ``mixed_batch_spec(seed)``: per-process point counts ``round(10**U(3,6))`` and
   centre-of-mass energies ``sqrt(s) ~ U(5,30)`` for n = 1..6.
 
@@ -113,6 +116,59 @@ def compton_lab_angles(theta: np.ndarray, phi: np.ndarray, omega: float = 1.0) -
     mom[15] = w2 * ct
     mom[8:12] = mom[0:4] + mom[4:8] - mom[12:16]
     return np.ascontiguousarray(mom)
+
+
+def crossed_inputs(seed: int, n_in: int, n_points: int, with_helicities: bool = False,
+                   omega_lo: float = 0.5, omega_hi: float = 2.0):
+    """Momenta of e- gamma^n_in -> e- gamma (the Table I orientation), SoA
+    ``[4(n_in+3)][N]`` in the order [e-_in, gamma_in_1..n_in, e-_out, gamma_out].
+
+    The electron is at rest (m = 1).  Incoming photon i has energy
+    omega_i ~ U(omega_lo, omega_hi) and an isotropic direction.  The outgoing
+    photon is isotropic in the centre-of-mass frame of the total momentum P,
+    with energy (s - m^2) / (2 sqrt(s)) there, and is boosted back along
+    P/P^0; the outgoing electron is P minus that photon.  Draws 3 n_in + 2
+    uniform rows, then (optionally) one helicity code < 2^(n_in+3) per point.
+    Returns ``(mom, hel)``.
+    """
+    g = rng_for(seed)
+    u = uniforms(seed, 3 * n_in + 2, n_points, rng=g)
+    m = ELECTRON_MASS
+    npart = n_in + 3
+    mom = np.zeros((4 * npart, n_points), dtype=np.float64)
+    mom[0] = m
+    for i in range(n_in):
+        w = omega_lo + (omega_hi - omega_lo) * u[3 * i]
+        ct = 2.0 * u[3 * i + 1] - 1.0
+        st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+        ph = 2.0 * math.pi * u[3 * i + 2]
+        r = 4 * (1 + i)
+        mom[r] = w
+        mom[r + 1] = w * st * np.cos(ph)
+        mom[r + 2] = w * st * np.sin(ph)
+        mom[r + 3] = w * ct
+    P = mom[0:4 * (n_in + 1)].reshape(n_in + 1, 4, n_points).sum(axis=0)
+    s = P[0] ** 2 - P[1] ** 2 - P[2] ** 2 - P[3] ** 2
+    rs = np.sqrt(s)
+    q = (s - m * m) / (2.0 * rs)
+    ct = 2.0 * u[3 * n_in] - 1.0
+    st = np.sqrt(np.maximum(0.0, 1.0 - ct * ct))
+    ph = 2.0 * math.pi * u[3 * n_in + 1]
+    kc = np.stack([q * st * np.cos(ph), q * st * np.sin(ph), q * ct])
+    beta = P[1:] / P[0]
+    gam = P[0] / rs
+    bk = (beta * kc).sum(axis=0)
+    k0 = gam * (q + bk)
+    kv = kc + beta * gam * (gam / (gam + 1.0) * bk + q)
+    ro = 4 * (n_in + 2)
+    mom[ro] = k0
+    mom[ro + 1:ro + 4] = kv
+    re = 4 * (n_in + 1)
+    mom[re:re + 4] = P - mom[ro:ro + 4]
+    hel = None
+    if with_helicities:
+        hel = g.integers(0, 1 << npart, size=n_points, dtype=np.int64).astype(np.uint32)
+    return np.ascontiguousarray(mom), hel
 
 
 def mixed_batch_spec(seed: int, n_values=(1, 2, 3, 4, 5, 6)):

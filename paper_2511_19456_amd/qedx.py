@@ -62,20 +62,28 @@ class QedProcess:
     mode: 'sum' (all 2^(n+3) spin/polarisation configurations) or 'per_point'
     (one configuration per point from a uint32 code).  precision: 'fp64' or
     'fp32c' (FP32 currents with compensated diagram sum, FP64 kinematics).
+    n_in > 1 gives the crossed process e- gamma^n_in -> e- gamma^n (Table I
+    uses n = 1): particle order [e-_in, gamma_in..., e-_out, gamma_out...],
+    eval only (no RAMBO, no gradient, no batches).
     """
 
     def __init__(self, n: int, mode: str = "sum", precision: str = "fp64",
-                 variant: Optional[QedVariant] = None):
+                 variant: Optional[QedVariant] = None, n_in: int = 1):
         _need_gpu()
         L = lib()
         self.n = int(n)
+        self.n_in = int(n_in)
         self.mode = mode
         self.precision = precision
-        self.n_particles = self.n + 3
+        self.n_particles = self.n + self.n_in + 2
         h = ctypes.c_void_p()
         vp = ctypes.byref(variant) if variant is not None else None
         torch.cuda.current_device()
-        check(L.qed_process_create(self.n, _MODES[mode], _PRECS[precision], vp, ctypes.byref(h)))
+        if self.n_in == 1:
+            check(L.qed_process_create(self.n, _MODES[mode], _PRECS[precision], vp, ctypes.byref(h)))
+        else:
+            check(L.qed_process_create_crossed(self.n_in, self.n, _MODES[mode], _PRECS[precision], vp,
+                                               ctypes.byref(h)))
         self._h = h
 
     def __del__(self):
@@ -102,7 +110,7 @@ class QedProcess:
 
     def eval(self, momenta: torch.Tensor, hel: Optional[torch.Tensor] = None,
              out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """|M|^2 for SoA momenta [4(n+3), N] (float64, device) -> [N] float64."""
+        """|M|^2 for SoA momenta [4(n+n_in+2), N] (float64, device) -> [N] float64."""
         _dev_tensor(momenta, torch.float64, 4 * self.n_particles, "momenta")
         N = momenta.shape[1]
         if hel is not None:

@@ -346,3 +346,42 @@ def test_partially_reduced_kernels(steps):
     ref = O.m2(ref_mom, n, "per_point", hel).numpy()
     tot = O.m2(ref_mom, n, "sum").numpy()
     assert (np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * tot / 128)).max() < 1e-10
+
+
+# Table I orientation e- gamma^n_in -> e- gamma^n_out (crossed processes).
+@pytest.mark.parametrize("n_in,n_out,mode,prec,rewrite,N", [
+    (2, 1, "sum", "fp64", 0, 515), (3, 1, "sum", "fp64", 0, 389), (4, 1, "sum", "fp64", 0, 150),
+    (3, 1, "sum", "fp32c", 0, 389), (2, 2, "sum", "fp64", 0, 300),
+    (2, 1, "per_point", "fp64", 0, 777), (3, 1, "per_point", "fp64", 0, 601), (4, 1, "per_point", "fp64", 0, 300),
+    (5, 1, "per_point", "fp64", 0, 120), (6, 1, "per_point", "fp64", 0, 40), (6, 1, "per_point", "fp64", 1, 40),
+    (3, 1, "per_point", "fp32c", 0, 601), (6, 1, "per_point", "fp32c", 0, 40)])
+def test_crossed_processes(n_in, n_out, mode, prec, rewrite, N):
+    from paper_2511_19456_amd._lib import QedError
+    from paper_2511_19456_amd.qedx import QedProcess, make_variant
+    print(f"crossed n_in={n_in} n_out={n_out} {mode} {prec} rewrite={rewrite} N={N}", flush=True)
+    if n_out == 1:
+        mom, hel = inputs.crossed_inputs(200 + n_in, n_in, N, with_helicities=True)
+        pts = O.soa_to_points(mom)
+    else:
+        u, _ = inputs.rambo_inputs(201, 3, N)
+        m3 = O.momenta_from_uniforms(u, 9.0, 3)
+        pts = torch.cat([m3[:, :2], -m3[:, 3:4], m3[:, 2:3], m3[:, 4:]], dim=1)
+        mom = O.points_to_soa(pts).numpy()
+        hel = inputs.rng_for(202).integers(0, 1 << 6, size=N).astype(np.uint32)
+    npart = n_in + n_out + 2
+    var = make_variant(rewrite=1) if rewrite else None
+    p = QedProcess(n_out, mode, prec, var, n_in=n_in)
+    assert p.info()["n_in"] == n_in
+    md = torch.as_tensor(mom, device=DEV)
+    tot = O.m2(mom, n_out, "sum", n_in=n_in).numpy()
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    if mode == "sum":
+        got = p.eval(md).cpu().numpy()
+        assert _rel(got, tot).max() < tol
+    else:
+        got = p.eval(md, torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
+        ref = O.m2(mom, n_out, "per_point", hel, n_in=n_in).numpy()
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * tot / (1 << npart))
+        assert err.max() < tol
+    with pytest.raises(QedError):
+        p.rambo(torch.zeros(4 * (n_out + 1), 4, dtype=torch.float64, device=DEV), 10.0)

@@ -10,6 +10,7 @@ import os
 
 import numpy as np
 import pytest
+import torch
 
 from oracle import qed_oracle as O
 from paper_2511_19456_amd import inputs
@@ -210,3 +211,31 @@ def test_partial_reduction_keeps_the_computation(steps):
     if steps == total:
         fix = Q.graph_counts(n, split=2, reduced=False)
         assert c["total"] < fix["total"] and c["S2"] == 120
+
+
+@pytest.mark.parametrize("n_in,n_out,reduced", [(2, 1, False), (2, 1, True), (3, 1, True), (3, 1, 2),
+                                                (2, 2, True), (4, 1, True)])
+def test_crossed_graph_equals_oracle(n_in, n_out, reduced):
+    """The graph of e- gamma^n_in -> e- gamma^n_out (the Table I orientation)
+    evaluates to the oracle's |M|^2, per configuration and summed."""
+    N = 16
+    if n_out == 1:
+        mom, hel = inputs.crossed_inputs(41 + n_in, n_in, N, with_helicities=True)
+        pts = O.soa_to_points(mom)
+    else:
+        # physical e- gamma -> e- 3gamma points with one outgoing photon crossed in
+        u, _ = inputs.rambo_inputs(43, 3, N)
+        m3 = O.momenta_from_uniforms(u, 9.0, 3)
+        pts = torch.cat([m3[:, :2], -m3[:, 3:4], m3[:, 2:3], m3[:, 4:]], dim=1)
+        hel = inputs.rng_for(44).integers(0, 1 << 6, size=N).astype(np.uint32)
+    npart = n_in + n_out + 2
+    flat = pts.numpy().reshape(N, 4 * npart)
+    proc = O.Process(n_out, n_in=n_in)
+    tot = O.m2_sum(pts, proc).numpy()
+    scale = tot / (1 << npart)
+    got = Q.graph_interpret(n_out, flat, hel, n_in=n_in, reduced=reduced)
+    ref = O.m2_per_point(pts, torch.as_tensor(hel.astype(np.int64)), proc).numpy()
+    assert np.max(np.abs(got - ref) / np.maximum(ref, 1e-3 * scale)) < 1e-11
+    all_mask = (1 << npart) - 1
+    got_s = Q.graph_interpret(n_out, flat, None, n_in=n_in, enum_mask=all_mask, reduced=reduced)
+    assert np.max(np.abs(got_s / tot - 1)) < 1e-11

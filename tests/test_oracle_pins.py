@@ -390,3 +390,122 @@ def test_gradient_matches_central_differences():
     err = np.linalg.norm(g - fd, axis=0) / np.linalg.norm(g, axis=0)
     assert err.max() < 1e-6
     assert torch.allclose(val, O.logm2_value(u, sqrt_s, n), rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# P11: the paper's orientation e- gamma^n_in -> e- gamma^n_out (Sec. III,
+# Table I) by crossing.  Crossing an incoming photon of momentum k into an
+# outgoing one of momentum -k keeps every propagator and every vertex; with
+# real linear polarisations eps(-k) = +-eps(k) (the transverse basis of -k is
+# that of k up to a sign), so each |A_h|^2 is unchanged once the helicity bits
+# follow their particles.  This ties the crossed oracle to the pinned
+# one-incoming-photon oracle.
+# ---------------------------------------------------------------------------
+def _crossed_points(n_in, N, seed):
+    mom, _ = inputs.crossed_inputs(seed, n_in, N)
+    return O.soa_to_points(mom)
+
+
+def _move_particle(mom, hel, src, dst, negate):
+    """Reorder particle src to position dst (momentum negated if asked), with
+    its helicity bit."""
+    order = list(range(mom.shape[1]))
+    order.pop(src)
+    order.insert(dst, src)
+    m2 = mom[:, order, :].clone()
+    if negate:
+        m2[:, dst, :] = -m2[:, dst, :]
+    h2 = torch.zeros_like(hel)
+    for new, old in enumerate(order):
+        h2 |= ((hel >> old) & 1) << new
+    return m2, h2
+
+
+@pytest.mark.parametrize("n_in", [2, 3])
+def test_crossing_incoming_photon_to_outgoing(n_in):
+    """e- gamma^n_in -> e- gamma  vs  e- gamma^(n_in-1) -> e- gamma^2 with the
+    last incoming photon crossed."""
+    mom = _crossed_points(n_in, 12, 70 + n_in)
+    pa = O.Process(1, n_in=n_in)
+    pb = O.Process(2, n_in=n_in - 1)
+    hel = O.all_helicities(mom.shape[0], pa)
+    A = O.amplitudes(mom, hel, pa)
+    # particle n_in (last incoming photon) moves to just after e-_out
+    mb, hb = _move_particle(mom, hel, n_in, n_in + 1, True)
+    B = O.amplitudes(mb, hb, pb)
+    scale = (A.abs() ** 2).sum(-1, keepdim=True)
+    assert float(((A.abs() ** 2 - B.abs() ** 2).abs() / scale).max()) < 1e-12
+    assert float((A.abs() ** 2).max() / scale.min()) > 1e-6  # non-trivial
+
+
+def test_crossing_outgoing_photon_to_incoming():
+    """Physical e- gamma -> e- 3gamma points crossed into e- gamma^2 -> e- gamma^2."""
+    mom = rand_momenta(3, 12, 9.0, 81)
+    pa = O.Process(3)
+    pb = O.Process(2, n_in=2)
+    hel = O.all_helicities(mom.shape[0], pa)
+    A = O.amplitudes(mom, hel, pa)
+    # first outgoing photon (particle 3) becomes the second incoming one (position 2)
+    mb, hb = _move_particle(mom, hel, 3, 2, True)
+    B = O.amplitudes(mb, hb, pb)
+    scale = (A.abs() ** 2).sum(-1, keepdim=True)
+    assert float(((A.abs() ** 2 - B.abs() ** 2).abs() / scale).max()) < 1e-12
+    sa = O.m2_sum(mom, pa)
+    sb = O.m2_sum(mb, pb)
+    assert float(((sa - sb).abs() / sa).max()) < 1e-12
+
+
+@pytest.mark.parametrize("n_in", [2, 3])
+def test_ward_identity_incoming_photons(n_in):
+    proc = O.Process(1, n_in=n_in)
+    mom = _crossed_points(n_in, 8, 90 + n_in)
+    N = mom.shape[0]
+    hel = O.all_helicities(N, proc)
+    K = hel.shape[1]
+    for j, pi in enumerate(proc.photon_idx):
+        kt = (proc.photon_sign[j] * mom[:, pi, :]).to(C128)[:, None, :].expand(N, K, 4)
+        A, absum = O.amplitudes(mom, hel, proc, photon_override={j: kt}, want_abs_terms=True)
+        assert float((A.abs() / absum).max()) < 1e-12
+    A0, ab0 = O.amplitudes(mom, hel, proc, want_abs_terms=True)
+    assert float((A0.abs() / ab0).max()) > 1e-3
+
+
+@pytest.mark.parametrize("n_in", [2, 3])
+def test_bose_symmetry_incoming_photons(n_in):
+    proc = O.Process(1, n_in=n_in)
+    mom = _crossed_points(n_in, 16, 100 + n_in)
+    hel = O.all_helicities(mom.shape[0], proc)
+    A = O.amplitudes(mom, hel, proc)
+    # swap the first and last incoming photons with their helicity bits
+    a, b = 1, n_in
+    mom2 = mom.clone()
+    mom2[:, a], mom2[:, b] = mom[:, b], mom[:, a]
+    h2 = hel & ~((1 << a) | (1 << b))
+    h2 |= ((hel >> a) & 1) << b
+    h2 |= ((hel >> b) & 1) << a
+    A2 = O.amplitudes(mom2, h2, proc)
+    scale = (A.abs() ** 2).sum(-1, keepdim=True)
+    assert float(((A.abs() ** 2 - A2.abs() ** 2).abs() / scale).max()) < 1e-13
+
+
+@pytest.mark.parametrize("n_in", [2, 4])
+def test_lorentz_invariance_crossed(n_in):
+    proc = O.Process(1, n_in=n_in)
+    mom = _crossed_points(n_in, 16, 110 + n_in)
+    L = _random_lorentz(120 + n_in)
+    mom2 = torch.einsum("ij,npj->npi", L, mom)
+    a = O.m2_sum(mom, proc)
+    b = O.m2_sum(mom2, proc)
+    assert float(((a - b).abs() / a).max()) < 1e-11
+
+
+def test_crossed_inputs_are_physical():
+    for n_in in (1, 2, 5):
+        mom = _crossed_points(n_in, 64, 130 + n_in)
+        msq = mom[..., 0] ** 2 - (mom[..., 1:] ** 2).sum(-1)
+        masses = torch.zeros(n_in + 3, dtype=F64)
+        masses[0] = masses[n_in + 1] = 1.0
+        assert float((msq - masses ** 2).abs().max()) < 1e-12
+        bal = mom[:, :n_in + 1].sum(1) - mom[:, n_in + 1:].sum(1)
+        assert float(bal.abs().max()) < 1e-12
+        assert bool((mom[..., 0] > 0).all())

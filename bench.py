@@ -408,6 +408,62 @@ def extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom_n3):
         return {"ms": ms, "points_per_s": wl["N"] / (ms * 1e-3), "ms_forward_only": ms_f,
                 "grad_over_forward": ms / ms_f}
     _leg(legs, "grad_n4_sum_fp64_2p18", want, grad)
+
+    def table1_crossed():
+        """The paper's Table I processes e- gamma^n -> e- gamma, one random
+        configuration per point, FP64, 2^20 points each (crossed kinematics)."""
+        N = 1 << 20
+        rows = []
+        for n_in in range(1, 7):
+            mom, hel = inputs.crossed_inputs(300 + n_in, n_in, N, with_helicities=True)
+            p = QedProcess(1, "per_point", "fp64", n_in=n_in)
+            md = torch.as_tensor(mom, device=dev)
+            hd = torch.as_tensor(hel.astype(np.int32), device=dev)
+            o = torch.empty(N, dtype=torch.float64, device=dev)
+            ms = time_launches(lambda: p.eval(md, hd, out=o), steps, 2)
+            inf = p.info()
+            rows.append({"n": n_in, "ms": ms, "ns_per_point": ms * 1e6 / N, "points_per_s": N / (ms * 1e-3),
+                         "nodes_unreduced": inf["nodes_unreduced"], "nodes_reduced": inf["nodes_reduced"],
+                         "flops_per_point": inf["flops_per_point"],
+                         "alg_tflops": inf["flops_per_point"] * N / (ms * 1e-3) / 1e12})
+        return {"process": "e- gamma^n -> e- gamma, per point, FP64, 2^20 points", "rows": rows}
+    _leg(legs, "table1_crossed_per_point_2p20", want, table1_crossed)
+
+    def fp64_pipes():
+        """FP64 vector pipe, FP64 matrix pipe (v_mfma_f64_16x16x4) and both at
+        once: achievable rates on this chip, and whether the two overlap."""
+        from paper_2511_19456_amd._lib import check, lib
+        blocks = 2048                      # 8 waves per SIMD
+        it_v, it_m = 60000, 8000
+        mm, cc = 0.999999, 1e-6
+        av = torch.arange(64, dtype=torch.float64, device=dev) / 64.0
+        bv = torch.arange(64, dtype=torch.float64, device=dev) / 128.0
+        ov = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+        om = torch.empty(blocks * 1024, dtype=torch.float64, device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+
+        def run(kind):
+            if kind == 0:
+                check(lib().qed_pipe_probe(0, blocks, it_v, 0, mm, cc, None, None, ov.data_ptr(), None, stream))
+            elif kind == 1:
+                check(lib().qed_pipe_probe(1, blocks, it_m, 0, mm, cc, av.data_ptr(), bv.data_ptr(),
+                                           om.data_ptr(), None, stream))
+            else:
+                check(lib().qed_pipe_probe(2, blocks, it_v, it_m, mm, cc, av.data_ptr(), bv.data_ptr(),
+                                           ov.data_ptr(), om.data_ptr(), stream))
+        waves = blocks * 4
+        fl_v = waves * 64 * 16.0 * it_v            # 8 FMA chains per lane
+        fl_m = waves * 4 * 2048.0 * it_m           # 4 MFMA per step per wave
+        t0 = time_launches(lambda: run(0), 5, 1)
+        t1 = time_launches(lambda: run(1), 5, 1)
+        t2 = time_launches(lambda: run(2), 5, 1)
+        half = 0.5 * (t0 + t1)                     # the mixed launch does half of each
+        return {"vector_ms": t0, "vector_tflops": fl_v / (t0 * 1e-3) / 1e12,
+                "matrix_ms": t1, "matrix_tflops": fl_m / (t1 * 1e-3) / 1e12,
+                "mixed_ms": t2, "mixed_tflops": 0.5 * (fl_v + fl_m) / (t2 * 1e-3) / 1e12,
+                "serial_estimate_ms": half, "overlap": half / t2,
+                "peak_tflops": FP64_VECTOR_PEAK_TFLOPS}
+    _leg(legs, "fp64_pipes", want, fp64_pipes)
     return legs
 
 

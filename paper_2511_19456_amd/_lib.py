@@ -76,6 +76,9 @@ SIGNATURES = {
                              ctypes.POINTER(c_double)]),
     "qed_prebuild_crossed": (c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(QedVariant),
                                      ctypes.POINTER(c_double)]),
+    "qed_pipe_probe": (c_int, [c_int, c_int64, c_int64, c_int64, c_double, c_double, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_void_p]),
+    "qed_pipe_probe_prebuild": (c_int, [ctypes.POINTER(c_double)]),
     "qed_graph_grad_interpret": (c_int, [c_int, c_int, c_int, c_void_p, c_int64, c_void_p, c_void_p]),
     "qed_rambo_vjp_host": (c_int, [c_int, c_void_p, c_double, c_void_p, c_int64, c_void_p, c_void_p]),
     "qed_graph_partial": (c_int, [c_int, c_int, c_int64, ctypes.c_uint64, c_void_p, c_void_p, c_int64, c_void_p,

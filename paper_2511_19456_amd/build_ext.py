@@ -29,7 +29,7 @@ LIB = os.path.join(PKG, "libqedx.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["qedx_dag.cpp", "qedx_emit.cpp", "qedx_kernels.cpp", "qedx_runtime.cpp", "qedx_batch.cpp",
-                "qedx_hosttools.cpp"]
+                "qedx_hosttools.cpp", "qedx_probe.cpp"]
 DEVICE_HEADERS = ["qedx_device.h", "qedx_rambo.h"]
 
 
@@ -175,6 +175,19 @@ def prebuild_batches(verbose: bool = True) -> None:
                 raise RuntimeError(f"batch prebuild failed for {spec}: {err}")
 
 
+def prebuild_probe(verbose: bool = True) -> None:
+    lib = ctypes.CDLL(LIB)
+    lib.qed_pipe_probe_prebuild.argtypes = [ctypes.POINTER(ctypes.c_double)]
+    lib.qed_pipe_probe_prebuild.restype = ctypes.c_int
+    lib.qed_last_error.restype = ctypes.c_char_p
+    ms = ctypes.c_double(0.0)
+    rc = lib.qed_pipe_probe_prebuild(ctypes.byref(ms))
+    if rc:
+        raise RuntimeError(f"probe prebuild failed: {lib.qed_last_error().decode()}")
+    if verbose:
+        print(f"[qedx build] FP64 pipe probe: compile={ms.value / 1e3:.1f}s", flush=True)
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--no-kernels", action="store_true")
@@ -184,6 +197,7 @@ def main(argv=None) -> None:
     if not a.no_kernels:
         prebuild_kernels(jobs=a.jobs)
         prebuild_batches()
+        prebuild_probe()
 
 
 if __name__ == "__main__":

@@ -385,3 +385,45 @@ def test_crossed_processes(n_in, n_out, mode, prec, rewrite, N):
         assert err.max() < tol
     with pytest.raises(QedError):
         p.rambo(torch.zeros(4 * (n_out + 1), 4, dtype=torch.float64, device=DEV), 10.0)
+
+
+def test_fp64_pipe_probe_closed_forms():
+    """The pipe probe's kernels do the work they are timed for: the vector
+    chains match the closed form of a <- a m + c, the matrix chains 4 iters A.B
+    with the stated operand and result lane layouts (dyadic inputs: exact)."""
+    from paper_2511_19456_amd._lib import check, lib
+    blocks, it_v, it_m = 3, 1000, 64
+    mm, cc = 0.999, 0.001
+    av = (torch.arange(64, dtype=torch.float64) + 1) / 64.0
+    bv = (torch.arange(64, dtype=torch.float64) * 3 + 1) / 128.0
+    a_d, b_d = av.to(DEV), bv.to(DEV)
+    ov = torch.full((blocks * 256,), -1.0, dtype=torch.float64, device=DEV)
+    om = torch.full((blocks * 1024,), -1.0, dtype=torch.float64, device=DEV)
+    st = torch.cuda.current_stream().cuda_stream
+    lane = np.arange(blocks * 256) % 64
+    mn = mm ** it_v
+    chains = sum(mn * (lane + j) + cc * (1 - mn) / (1 - mm) for j in range(8))
+    A = av.numpy().reshape(4, 16).T          # A[i][k] = a[i + 16 k]
+    B = bv.numpy().reshape(4, 16)            # B[k][j] = b[j + 16 k]
+    C = 4 * it_m * (A @ B)
+    lanes = np.arange(blocks * 256)
+    expect_m = np.zeros(blocks * 1024)
+    for r in range(4):
+        # item r of lane l holds row l/16 + 4r, column l%16
+        expect_m[4 * lanes + r] = C[(lanes % 64) // 16 + 4 * r, lanes % 16]
+    check(lib().qed_pipe_probe(0, blocks, it_v, 0, mm, cc, None, None, ov.data_ptr(), None, st))
+    torch.cuda.synchronize()
+    assert np.max(np.abs(ov.cpu().numpy() / chains - 1)) < 1e-12
+    check(lib().qed_pipe_probe(1, blocks, it_m, 0, mm, cc, a_d.data_ptr(), b_d.data_ptr(), om.data_ptr(),
+                               None, st))
+    torch.cuda.synchronize()
+    assert np.array_equal(om.cpu().numpy(), expect_m)
+    ov.fill_(-1.0)
+    om.fill_(-1.0)
+    check(lib().qed_pipe_probe(2, blocks, it_v, it_m, mm, cc, a_d.data_ptr(), b_d.data_ptr(), ov.data_ptr(),
+                               om.data_ptr(), st))
+    torch.cuda.synchronize()
+    even = ((lanes // 64) % 2) == 0
+    got_v, got_m = ov.cpu().numpy(), om.cpu().numpy().reshape(-1, 4)
+    assert np.max(np.abs(got_v[even] / chains[even] - 1)) < 1e-12
+    assert np.array_equal(got_m[~even], expect_m.reshape(-1, 4)[~even])

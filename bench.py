@@ -116,14 +116,20 @@ def alg_flops(n, mode, rewrite=0):
 def rel_err_stats(a, b, per_point=False):
     """Relative error of a against b.  One configuration per point can nearly
     vanish where diagrams cancel, so there the denominator is floored at 1e-3
-    of the median |b| (the same reading the parity tests use)."""
+    of the median |b| (the same reading the parity tests use); the plain
+    relative maximum is reported beside it."""
     import torch
     den = b.abs()
+    plain = ((a - b).abs() / den).double()
     if per_point:
         den = torch.clamp(den, min=1e-3 * den.median().item())
     r = ((a - b).abs() / den).double()
     q = torch.quantile(r[: 1 << 20].float(), torch.tensor([0.5, 0.99], device=r.device)).tolist()
-    return {"max": r.max().item(), "p99": q[1], "median": q[0], "frac_above_1e-4": (r > 1e-4).double().mean().item()}
+    out = {"max": r.max().item(), "p99": q[1], "median": q[0], "frac_above_1e-4": (r > 1e-4).double().mean().item()}
+    if per_point:
+        out["max_plain_relative"] = plain.max().item()
+        out["points_plain_above_1e-4"] = int((plain > 1e-4).sum().item())
+    return out
 
 
 def main():
@@ -271,6 +277,13 @@ def extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom_n3):
             if prec == "fp32c" and "fp64_out" in p5:
                 r["err_vs_fp64_kernel"] = rel_err_stats(o, p5["fp64_out"], per_point=True)
                 r["speedup_vs_fp64"] = legs["n5_per_point_fp64_2p20"]["ms"] / ms
+                # the same kernel without the FP64 pass over ill-conditioned points
+                from paper_2511_19456_amd.qedx import make_variant
+                q = QedProcess(5, "per_point", prec, make_variant(fixup=-1))
+                o2 = torch.empty_like(o)
+                r["ms_without_fixup"] = time_launches(lambda: q.eval(m, h5d, out=o2), steps, 2)
+                r["err_without_fixup"] = rel_err_stats(o2, p5["fp64_out"], per_point=True)
+                r["fix_kappa"] = info["fix_kappa"]
             return r
         return run
     _leg(legs, "n5_per_point_fp64_2p20", want, n5("fp64"))
@@ -314,6 +327,10 @@ def extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom_n3):
                  "speedup_vs_plain_fp64": ms_p / ms_b}
             if err is not None:
                 r["max_rel_diff_vs_plain"] = err
+            else:
+                # FP32C batch against the plain FP64 kernels, over all points
+                r["err_vs_fp64_kernel"] = rel_err_stats(torch.cat(outs_b), torch.cat([pp[3] for pp in plain_procs]),
+                                                        per_point=True)
             return r
         return run
     def mixed_small():

@@ -29,9 +29,10 @@
  *  - On any error the function returns a nonzero status, writes nothing to
  *    the outputs, and qed_last_error() returns a message (thread-local).
  *  - N == 0 is a valid no-op.  Device memory is allocated only by
- *    qed_batch_plan_create (its tile table and counter) and by qed_eval_grad
- *    for n >= 4 (a workspace owned by the process handle, grown on demand and
- *    freed by qed_process_destroy).
+ *    qed_batch_plan_create (its tile table, counter and, for FP32C, the
+ *    fix-up list), by qed_eval_grad for n >= 4, and by qed_eval of FP32C
+ *    per-point processes (workspaces owned by the process handle, grown on
+ *    demand and freed by qed_process_destroy).
  */
 #ifndef QEDX_H
 #define QEDX_H
@@ -62,8 +63,11 @@ typedef enum { QED_HEL_SUM = 0, QED_HEL_PER_POINT = 1 } qed_hel_mode;
  * QED_FP32C: currents, vertices, propagator numerators and diagram values in
  * float32 with compensated (TwoSum) accumulation of the diagram sum;
  * momenta, propagator momenta and denominators, |A|^2 and the helicity sum in
- * float64.  Relative error against float64 is bounded by 1e-4 on the stated
- * workloads (measured, not guaranteed for arbitrary points). */
+ * float64.  Per-point processes recompute in float64 the points whose diagram
+ * sum cancels by more than fix_kappa (qed_variant), which keeps the relative
+ * error against float64 below 1e-4 on every point of the stated workloads
+ * (measured, not a proof for arbitrary points); helicity sums dilute the
+ * cancellation of single configurations and meet the bound without it. */
 typedef enum { QED_FP64 = 0, QED_FP32C = 1 } qed_precision;
 
 /* Kernel shape knobs (a zero field = library default for the process).
@@ -95,6 +99,13 @@ typedef struct {
                            Sec. III-D (kernel time against the number of reductions). */
   int32_t partial_steps;
   uint32_t partial_seed;
+  int32_t fixup;        /* FP32C per-point processes: 0 = default (on), < 0 = off.  The FP32C
+                           kernel also sums |diagram value|^2; where the square root of that
+                           sum exceeds fix_kappa * |A|, the diagram sum cancels beyond what
+                           FP32 currents resolve, the point is listed, and a second kernel
+                           recomputes the listed points in FP64 (qed_eval launches both on
+                           the stream). */
+  float fix_kappa;      /* cancellation threshold (0 = library default, 16) */
 } qed_variant;
 
 typedef struct {
@@ -111,6 +122,8 @@ typedef struct {
   char code_hash[24];        /* hash of the eval kernel's source, flags and target (changes with the code) */
   char kernel_name[48];      /* symbol of the eval kernel, qedx_eval_[i<n_in>]n<n>_<sum|pp>_<fp64|fp32c>[_d1][_k<steps>] */
   int32_t n_in;              /* incoming photons (1 unless created by qed_process_create_crossed) */
+  int32_t fixup;             /* 1 if the FP32C kernel has the FP64 fix-up pass */
+  double fix_kappa;          /* its cancellation threshold */
 } qed_info;
 
 /* Build the graph for n outgoing photons (1..6), reduce it, emit and compile
@@ -126,8 +139,8 @@ qed_status qed_process_create(int n, qed_hel_mode mode, qed_precision prec, cons
  * and graph; particle order [e-_in, gamma_in_1..n_in, e-_out, gamma_out_1..n_out],
  * so momenta are [4(n_in + n_out + 2)][N] and helicity bit i belongs to
  * particle i.  Incoming photons carry eps, outgoing eps* (equal: real linear
- * polarisations).  qed_eval and batches work as for one incoming photon;
- * qed_rambo and qed_eval_grad return UNSUPPORTED for n_in > 1. */
+ * polarisations).  qed_eval works as for one incoming photon; qed_rambo,
+ * qed_eval_grad and qed_batch_plan_create return UNSUPPORTED for n_in > 1. */
 qed_status qed_process_create_crossed(int n_in, int n_out, qed_hel_mode mode, qed_precision prec,
                                       const qed_variant* variant, qed_process** out);
 qed_status qed_process_destroy(qed_process* p);
@@ -138,7 +151,10 @@ qed_status qed_process_info(const qed_process* p, qed_info* out);
  * momenta: device, float64 [4(n+3)][N]; hel: device uint32 [N] in PER_POINT
  * mode and NULL in SUM mode; out: device float64 [N].
  * INVALID_ARG if N < 0, a required pointer is NULL while N > 0, or hel does not
- * match the mode. */
+ * match the mode.  FP32C per-point processes with the FP64 fix-up keep a
+ * device workspace of 4(N + 1) bytes (allocated, or grown, by the first call
+ * with a larger N; freed by qed_process_destroy); calls on one such process
+ * must not overlap, and N is limited to 2^32 - 1 for them. */
 qed_status qed_eval(const qed_process* p, const double* momenta, const uint32_t* hel, int64_t N, double* out,
                     void* stream);
 
@@ -181,9 +197,13 @@ typedef struct {
  * overwritten, after a device synchronisation; the choice is cached by plan
  * signature).  The plan copies the segment table to the device, allocates a
  * 256-byte tile counter, and instantiates a HIP graph of two kernel nodes
- * (counter clear, persistent kernel).  The segment buffers must stay valid
- * while the plan is launched.  Plans are not thread-safe: launches of one plan
- * on overlapping streams race on its counter. */
+ * (counter clear, persistent kernel).  FP32C plans (per-point processes with
+ * the FP64 fix-up) also allocate a list of 4(1 + 2 x total points) bytes and
+ * add two nodes (list clear, FP64 pass over the listed points); the threshold
+ * is the first segment's process's fix_kappa, and the total must stay below
+ * 2^31 points.  The segment buffers must stay valid while the plan is
+ * launched.  Plans are not thread-safe: launches of one plan on overlapping
+ * streams race on its counter. */
 qed_status qed_batch_plan_create(const qed_segment* segs, int nseg, int tile_points, qed_batch_plan** out);
 qed_status qed_batch_launch(qed_batch_plan* plan, void* stream);
 qed_status qed_batch_plan_destroy(qed_batch_plan* plan);

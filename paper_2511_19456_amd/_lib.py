@@ -27,7 +27,8 @@ class QedVariant(ctypes.Structure):
     _fields_ = [("lane_bits", c_uint32), ("loop_bits", c_uint32), ("block", ctypes.c_int32),
                 ("split", ctypes.c_int32), ("min_waves", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32),
-                ("partial", ctypes.c_int32), ("partial_steps", ctypes.c_int32), ("partial_seed", ctypes.c_uint32)]
+                ("partial", ctypes.c_int32), ("partial_steps", ctypes.c_int32), ("partial_seed", ctypes.c_uint32),
+                ("fixup", ctypes.c_int32), ("fix_kappa", ctypes.c_float)]
 
 
 class QedInfo(ctypes.Structure):
@@ -41,7 +42,8 @@ class QedInfo(ctypes.Structure):
                 ("create_ms_build", c_double), ("create_ms_reduce", c_double), ("create_ms_emit", c_double),
                 ("create_ms_compile", c_double), ("create_ms_load", c_double),
                 ("cache_hit", ctypes.c_int32), ("kernel_tag", ctypes.c_char * 160),
-                ("code_hash", ctypes.c_char * 24), ("kernel_name", ctypes.c_char * 48), ("n_in", ctypes.c_int32)]
+                ("code_hash", ctypes.c_char * 24), ("kernel_name", ctypes.c_char * 48), ("n_in", ctypes.c_int32),
+                ("fixup", ctypes.c_int32), ("fix_kappa", ctypes.c_double)]
 
 
 class QedSegment(ctypes.Structure):

@@ -77,7 +77,8 @@ class QedVariant(ctypes.Structure):
     _fields_ = [("lane_bits", ctypes.c_uint32), ("loop_bits", ctypes.c_uint32), ("block", ctypes.c_int32),
                 ("split", ctypes.c_int32), ("min_waves", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32),
-                ("partial", ctypes.c_int32), ("partial_steps", ctypes.c_int32), ("partial_seed", ctypes.c_uint32)]
+                ("partial", ctypes.c_int32), ("partial_steps", ctypes.c_int32), ("partial_seed", ctypes.c_uint32),
+                ("fixup", ctypes.c_int32), ("fix_kappa", ctypes.c_float)]
 
 
 # (n, mode, precision[, variant fields]) built ahead of time: SUM 0 / PER_POINT 1;

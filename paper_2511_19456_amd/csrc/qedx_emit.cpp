@@ -35,6 +35,7 @@ std::string variant_tag(const Variant& v, int n_out, int n_in) {
     << v.order << "_w" << v.min_waves;
   if (v.rewrite) o << "_d" << v.rewrite;
   if (v.partial) o << "_k" << v.partial_steps << "s" << v.partial_seed;
+  if (v.fixup) o << "_f" << v.fixup;
   return o.str();
 }
 
@@ -254,6 +255,11 @@ struct Emitter {
     if (v.prec == PREC_F64) {
       os << ind << "qx::dot_acc<double>(A" << acc << ", " << B << ", " << name(ops.first) << ");\n";
       st.flops_per_point += 32;
+    } else if (abs_sum) {
+      os << ind << "{ const qx::cx<float> x_ = qx::dot<float>(" << B << ", " << name(ops.first)
+         << "); qx::comp_acc<float>(A" << acc << ", C" << acc << ", x_); S" << acc
+         << " = fmaf(x_.r, x_.r, fmaf(x_.i, x_.i, S" << acc << ")); }\n";
+      st.flops_per_point += 30 + 14 + 2;
     } else {
       os << ind << "qx::comp_acc<float>(A" << acc << ", C" << acc << ", qx::dot<float>(" << B << ", "
          << name(ops.first) << "));\n";
@@ -262,6 +268,10 @@ struct Emitter {
     ++st.n_dot;
     fence(2);
   }
+
+  // FP32C per-point fix-up: sum |diagram value| beside the compensated sum
+  // and raise `fixflag` (declared by the kernel) on cancellation
+  bool abs_sum = false;
 
   std::vector<int> sum_nodes() const {
     std::vector<int> sums;
@@ -462,6 +472,7 @@ struct Emitter {
       acc_of_sum[sums[a]] = (int)a;
       os << ind << "qx::cx<" << T << "> A" << a << " = {" << T << "(0), " << T << "(0)};\n";
       if (v.prec != PREC_F64) os << ind << "qx::cx<float> C" << a << " = {0.0f, 0.0f};\n";
+      if (abs_sum) os << ind << "float S" << a << " = 0.0f;\n";
     }
     std::map<uint32_t, std::vector<int>> part;
     std::vector<uint32_t> order;
@@ -482,7 +493,10 @@ struct Emitter {
         os << ind << "acc += A" << a << ".r * A" << a << ".r + A" << a << ".i * A" << a << ".i;\n";
       } else {
         os << ind << "{ const double ar = (double)A" << a << ".r + (double)C" << a << ".r, ai = (double)A" << a
-           << ".i + (double)C" << a << ".i; acc += ar * ar + ai * ai; }\n";
+           << ".i + (double)C" << a << ".i; acc += ar * ar + ai * ai;";
+        if (abs_sum)
+          os << " if (!((double)S" << a << " <= fix_kappa * fix_kappa * (ar * ar + ai * ai))) fixflag = 1;";
+        os << " }\n";
       }
       st.flops_per_point += 4;
     }
@@ -896,6 +910,12 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   os << "// generated by qedx: " << variant_tag(v, d.proc.n_out, d.proc.n_in) << "\n";
   os << "#include <hip/hip_runtime.h>\n";
   os << device_header_text() << "\n";
+  if (v.fixup) {
+    if (v.prec != PREC_F32C || v.mode != HEL_PER_POINT)
+      throw std::invalid_argument("the FP64 fix-up is built for FP32C per-point kernels");
+    if (v.order & 16) throw std::invalid_argument("the FP64 fix-up excludes LDS staging");
+    e.abs_sum = true;
+  }
   if (v.order & 8) {
     e.slot = true;
     e.slot_tab = kname + "_slots";
@@ -904,7 +924,9 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   os << "extern \"C\" __global__ void __launch_bounds__(" << v.block;
   if (v.min_waves > 0) os << ", " << v.min_waves;
   os << ")\n" << kname
-     << "(const double* __restrict__ mom, const unsigned* __restrict__ hel, long long N, double* __restrict__ out)\n{\n";
+     << "(const double* __restrict__ mom, const unsigned* __restrict__ hel, long long N, double* __restrict__ out"
+     << (v.fixup ? ", double fix_kappa, unsigned* __restrict__ fix_cnt, unsigned* __restrict__ fix_list" : "")
+     << ")\n{\n";
   const std::string lds_mark = "  //@LDS@\n";
   os << lds_mark;
   os << "  const long long gid = (long long)blockIdx.x * " << v.block << " + threadIdx.x;\n";
@@ -913,10 +935,26 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   os << "  const long long ptc = pt < N ? pt : N - 1;\n";
   if (!e.local() && !e.slot && !e.loop_local()) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
+  if (v.fixup) os << "  int fixflag = 0;\n";
   std::string hrt = v.mode == HEL_PER_POINT ? "hel[ptc]" : Emitter::deposit("sub", v.lane_mask);
   e.lane_work(hrt);
   for (int o = 1; o < G; o <<= 1) os << "  acc += __shfl_xor(acc, " << o << ");\n";
-  os << "  if (pt < N && sub == 0u) out[pt] = acc;\n}\n";
+  if (v.fixup)
+    // one counter update per wave (ballot, then each flagged lane's rank
+    // among the flagged lanes below it)
+    os << "  if (pt < N && sub == 0u) out[pt] = acc;\n"
+       << "  const bool fx_ = fixflag && pt < N && sub == 0u;\n"
+       << "  const unsigned long long fm_ = __ballot(fx_);\n"
+       << "  if (fm_) {\n"
+       << "    const unsigned ln_ = __lane_id();\n"
+       << "    const unsigned ld_ = (unsigned)__ffsll((unsigned long long)fm_) - 1u;\n"
+       << "    unsigned base_ = 0u;\n"
+       << "    if (ln_ == ld_) base_ = atomicAdd(fix_cnt, (unsigned)__popcll(fm_));\n"
+       << "    base_ = __shfl(base_, (int)ld_);\n"
+       << "    if (fx_) fix_list[base_ + (unsigned)__popcll(fm_ & ((1ull << ln_) - 1ull))] = (unsigned)pt;\n"
+       << "  }\n}\n";
+  else
+    os << "  if (pt < N && sub == 0u) out[pt] = acc;\n}\n";
   // per point: every lane of the group does the body once per loop iteration
   e.st.flops_per_point *= (double)G * (double)(1 << popc(v.loop_mask));
   std::string src = os.str();
@@ -927,6 +965,25 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
       decl = "  __shared__ " + e.T + " qx_lds[" + std::to_string(e.lds_slots * 8 * v.block) + "];\n";
     size_t at = src.find(lds_mark);
     src.replace(at, lds_mark.size(), decl);
+  }
+  if (v.fixup) {
+    // FP64 pass over the points the FP32C kernel could not resolve
+    Variant v64 = v;
+    v64.prec = PREC_F64;
+    v64.fixup = 0;
+    EmitStats st64;
+    std::ostringstream fx;
+    fx << emit_body_function(d, v64, kname + "_b64", &st64) << "\n";
+    fx << "extern \"C\" __global__ void __launch_bounds__(64)\n"
+       << kname << "_fix_zero(unsigned* __restrict__ fix_cnt)\n{\n  if (threadIdx.x == 0) fix_cnt[0] = 0u;\n}\n";
+    fx << "extern \"C\" __global__ void __launch_bounds__(256)\n"
+       << kname << "_fix(const double* __restrict__ mom, const unsigned* __restrict__ hel, long long N, "
+       << "double* __restrict__ out, const unsigned* __restrict__ fix_cnt, const unsigned* __restrict__ fix_list)\n{\n"
+       << "  const long long cnt = (long long)fix_cnt[0];\n"
+       << "  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < cnt; i += (long long)gridDim.x * 256) {\n"
+       << "    const long long pt = (long long)fix_list[i];\n"
+       << "    out[pt] = " << kname << "_b64(mom, N, pt, hel[pt]);\n  }\n}\n";
+    src += fx.str();
   }
   e.st.lines = std::count(src.begin(), src.end(), '\n');
   if (stats) *stats = e.st;
@@ -1152,8 +1209,14 @@ std::string emit_body_function(const Dag& d, const Variant& v, const std::string
     e.slot_tab = fname + "_slots";
     e.emit_slot_table();
   }
+  if (v.fixup) {
+    if (v.prec != PREC_F32C || v.mode != HEL_PER_POINT)
+      throw std::invalid_argument("the FP64 fix-up is built for FP32C per-point bodies");
+    e.abs_sum = true;
+  }
   os << "static __device__ double " << fname
-     << "(const double* __restrict__ mom, long long N, long long ptc, unsigned hrt_in)\n{\n";
+     << "(const double* __restrict__ mom, long long N, long long ptc, unsigned hrt_in"
+     << (v.fixup ? ", int& fixflag, double fix_kappa" : "") << ")\n{\n";
   if (!e.local() && !e.slot) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
   e.lane_work("hrt_in");

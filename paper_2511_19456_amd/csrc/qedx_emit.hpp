@@ -30,6 +30,7 @@ struct Variant {
   int partial = 0;      // 1: unsplit graph after partial_steps single reductions only
   int partial_steps = 0;
   uint32_t partial_seed = 0;
+  int fixup = 0;        // 1: FP32C per-point kernel flags ill-conditioned points for an FP64 pass
 };
 
 struct EmitStats {
@@ -50,6 +51,17 @@ Dag graph_for(const Process& proc, const Variant& v, double* t_build, double* t_
 //   extern "C" __global__ void <kname>(const double* mom, const unsigned* hel,
 //                                      long long N, double* out)
 // mom: [4*npart][N] SoA (row = 4*particle + mu), out: [N].
+// With v.fixup (FP32C, per point) the kernel takes three more arguments,
+// (double fix_kappa, unsigned* fix_cnt, unsigned* fix_list), also sums
+// |diagram value|^2 beside the compensated sum, and appends the point index
+// to fix_list (fix_cnt counts) where sqrt of that sum exceeds
+// fix_kappa * |A|: a cancellation the FP32 currents cannot resolve to the
+// stated bound.  The module then also holds
+//   extern "C" __global__ void <kname>_fix_zero(unsigned* fix_cnt)   (one lane clears it)
+//   extern "C" __global__ void <kname>_fix(const double* mom, const unsigned* hel,
+//       long long N, double* out, const unsigned* fix_cnt, const unsigned* fix_list)
+// the latter recomputing the listed points with the FP64 body of the same
+// graph (grid-stride loop over the list, any grid).
 std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* st);
 
 // Gradient kernel (SUM mode, FP64, partition-local blocks, no loop bits):
@@ -78,7 +90,9 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
 // Device function text of one process body (used by the mixed batch module):
 //   __device__ double <fname>(const double* mom, long long N, long long pt,
 //                             unsigned hrt)
-// returning the per-lane partial sum of |A|^2.
+// returning the per-lane partial sum of |A|^2.  With v.fixup (FP32C, per
+// point) it takes (..., int& fixflag, double fix_kappa) and sets fixflag as
+// the eval kernel's fix-up test does.
 std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* st);
 
 // The device header text (inlined into every generated unit).

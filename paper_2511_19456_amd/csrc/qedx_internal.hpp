@@ -27,6 +27,10 @@ struct qed_process {
   int lanes = 1;
   hipModule_t mod = nullptr;
   hipFunction_t f_eval = nullptr;
+  hipFunction_t f_fix = nullptr;  // FP64 pass of FP32C per-point kernels (null if none)
+  hipFunction_t f_fix_zero = nullptr;
+  unsigned* fix_ws = nullptr;     // [count, list of N point indices], grown on demand
+  size_t fix_bytes = 0;
   hipModule_t mod_aux = nullptr;  // RAMBO and gradient kernels
   hipFunction_t f_rambo = nullptr;
   hipFunction_t f_grad = nullptr;
@@ -40,10 +44,9 @@ struct qed_process {
   size_t ws_bytes = 0;
   std::string eval_src;
   ~qed_process() {
-    if (ws) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(ws);
-    }
+    if (ws || fix_ws) (void)hipDeviceSynchronize();
+    if (ws) (void)hipFree(ws);
+    if (fix_ws) (void)hipFree(fix_ws);
     if (mod) (void)hipModuleUnload(mod);
     if (mod_aux) (void)hipModuleUnload(mod_aux);
   }

@@ -289,8 +289,29 @@ static void default_variant(int n, int nin, qed_hel_mode mode, qed_precision pre
   }
 }
 
+static const double kFixKappa = 16.0;
+
+static qed_status make_variant_shape(int n, int nin, qed_hel_mode mode, qed_precision prec, const qed_variant* qv,
+                                     Variant& v);
+
+// Kernel shape plus the FP64 fix-up flag of FP32C per-point kernels.
 static qed_status make_variant(int n, int nin, qed_hel_mode mode, qed_precision prec, const qed_variant* qv,
-                               Variant& v) {
+                               Variant& v, double* fix_kappa = nullptr) {
+  qed_status s = make_variant_shape(n, nin, mode, prec, qv, v);
+  if (s) return s;
+  bool custom = qv && !qv->use_defaults;
+  v.fixup = (prec == QED_FP32C && mode == QED_HEL_PER_POINT && !(v.order & 16) && !v.partial &&
+             !(custom && qv->fixup < 0))
+                ? 1
+                : 0;
+  double k = custom && qv->fix_kappa != 0.0f ? (double)qv->fix_kappa : kFixKappa;
+  if (!(k >= 1.0) || !std::isfinite(k)) return fail(QED_ERR_INVALID_ARG, "fix_kappa must be >= 1");
+  if (fix_kappa) *fix_kappa = k;
+  return QED_OK;
+}
+
+static qed_status make_variant_shape(int n, int nin, qed_hel_mode mode, qed_precision prec, const qed_variant* qv,
+                                     Variant& v) {
   default_variant(n, nin, mode, prec, v);
   const int P = n + nin, npart = P + 2;
   if (qv && !qv->use_defaults) {
@@ -349,8 +370,11 @@ static qed_status build_source(int n, int nin, qed_hel_mode mode, qed_precision 
   if (n < 1 || nin < 1 || n + nin > 7) return fail(QED_ERR_UNSUPPORTED, "need n_out >= 1, n_in >= 1, n_in + n_out <= 7");
   if (mode != QED_HEL_SUM && mode != QED_HEL_PER_POINT) return fail(QED_ERR_INVALID_ARG, "bad helicity mode");
   if (prec != QED_FP64 && prec != QED_FP32C) return fail(QED_ERR_INVALID_ARG, "bad precision");
-  qed_status s = make_variant(n, nin, mode, prec, qv, v);
+  double fk = 0;
+  qed_status s = make_variant(n, nin, mode, prec, qv, v, &fk);
   if (s) return s;
+  info.fixup = v.fixup;
+  info.fix_kappa = v.fixup ? fk : 0.0;
   proc = Process::make(n, nin);
   try {
     double tb = 0, tr = 0;
@@ -471,6 +495,11 @@ static qed_status process_create(int nin, int n, qed_hel_mode mode, qed_precisio
   auto t0 = std::chrono::steady_clock::now();
   HIPCHK(hipModuleLoadData(&p->mod, co.data()));
   HIPCHK(hipModuleGetFunction(&p->f_eval, p->mod, p->info.kernel_name));
+  if (p->var.fixup) {
+    std::string fx = std::string(p->info.kernel_name) + "_fix";
+    HIPCHK(hipModuleGetFunction(&p->f_fix, p->mod, fx.c_str()));
+    HIPCHK(hipModuleGetFunction(&p->f_fix_zero, p->mod, (fx + "_zero").c_str()));
+  }
   if (nin != 1) {  // RAMBO and the gradient are built for one incoming photon
     p->info.create_ms_load = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = p.release();
@@ -553,8 +582,37 @@ extern "C" qed_status qed_eval(const qed_process* p, const double* momenta, cons
   if (p->mode == QED_HEL_PER_POINT && !hel) return fail(QED_ERR_INVALID_ARG, "hel required in PER_POINT mode");
   if (N > (int64_t)1 << 40) return fail(QED_ERR_INVALID_ARG, "N too large");
   long long n = (long long)N;
-  void* args[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out};
-  return launch(p->f_eval, N * (int64_t)p->lanes, p->var.block, stream, args);
+  if (!p->f_fix) {
+    void* args[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out};
+    return launch(p->f_eval, N * (int64_t)p->lanes, p->var.block, stream, args);
+  }
+  // FP32C pass listing the ill-conditioned points, then the FP64 pass over
+  // the list (grid-stride, at most 1024 workgroups).  The list lives in a
+  // process-owned workspace of N + 1 words, grown here when N grows.
+  if (N > (int64_t)0xffffffffu) return fail(QED_ERR_INVALID_ARG, "N must be below 2^32 for the FP64 fix-up list");
+  qed_process* q = const_cast<qed_process*>(p);
+  size_t need = sizeof(unsigned) * ((size_t)N + 1);
+  if (q->fix_bytes < need) {
+    if (q->fix_ws) {
+      HIPCHK(hipDeviceSynchronize());
+      HIPCHK(hipFree(q->fix_ws));
+      q->fix_ws = nullptr;
+      q->fix_bytes = 0;
+    }
+    HIPCHK(hipMalloc((void**)&q->fix_ws, need));
+    q->fix_bytes = need;
+  }
+  unsigned* cnt = q->fix_ws;
+  unsigned* list = q->fix_ws + 1;
+  void* zargs[] = {(void*)&cnt};
+  qed_status s = launch(p->f_fix_zero, 64, 64, stream, zargs);
+  if (s) return s;
+  double kappa = p->info.fix_kappa;
+  void* args[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out, (void*)&kappa, (void*)&cnt, (void*)&list};
+  s = launch(p->f_eval, N * (int64_t)p->lanes, p->var.block, stream, args);
+  if (s) return s;
+  void* fargs[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out, (void*)&cnt, (void*)&list};
+  return launch(p->f_fix, std::min<int64_t>(N, 1024 * 256), 256, stream, fargs);
 }
 
 extern "C" qed_status qed_rambo(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N,

@@ -46,14 +46,16 @@ def _dev_tensor(t: torch.Tensor, dtype: torch.dtype, rows: int, name: str) -> to
 
 def make_variant(lane_bits: int = 0, loop_bits: int = 0, block: int = 0, split: int = 0,
                  min_waves: int = 0, order: int = 0, rewrite: int = 0,
-                 partial_steps: Optional[int] = None, partial_seed: int = 0) -> QedVariant:
+                 partial_steps: Optional[int] = None, partial_seed: int = 0,
+                 fixup: int = 0, fix_kappa: float = 0.0) -> QedVariant:
     """Kernel shape (fields of qed_variant); rewrite=1 adds the distributive
     rewrite after node reduction; partial_steps=k builds the paper's unsplit
-    graph after only k single node reductions (seeded random order).  Zero
-    fields take the library default."""
+    graph after only k single node reductions (seeded random order);
+    fixup=-1 turns off the FP64 pass of FP32C per-point kernels, fix_kappa sets
+    its cancellation threshold.  Zero fields take the library default."""
     part = partial_steps is not None
     return QedVariant(lane_bits, loop_bits, block, split, min_waves, order, 0, rewrite, int(part),
-                      int(partial_steps or 0), int(partial_seed))
+                      int(partial_steps or 0), int(partial_seed), int(fixup), float(fix_kappa))
 
 
 class QedProcess:

@@ -427,3 +427,35 @@ def test_fp64_pipe_probe_closed_forms():
     got_v, got_m = ov.cpu().numpy(), om.cpu().numpy().reshape(-1, 4)
     assert np.max(np.abs(got_v[even] / chains[even] - 1)) < 1e-12
     assert np.array_equal(got_m[~even], expect_m.reshape(-1, 4)[~even])
+
+
+@pytest.mark.parametrize("n,sqrt_s", [(3, 10.0), (5, 20.0)])
+def test_fp32c_fp64_fixup(n, sqrt_s):
+    """FP32C per-point kernels list the points whose diagram sum cancels
+    beyond what FP32 resolves and recompute them in FP64.  Against the FP64
+    kernel (itself pinned to the oracle), over calls with growing and
+    shrinking N (workspace reuse): relative error <= 1e-4 with the
+    denominator floored at 1e-3 of the median |M|^2 (the bench's reading for
+    configurations that nearly vanish), and <= 3e-4 without the floor."""
+    from paper_2511_19456_amd.qedx import make_variant
+    N = 1 << 16
+    u, h = inputs.rambo_inputs(5 + n, n, N, with_helicities=True)
+    p64 = _proc(n, "per_point", "fp64")
+    mom = p64.rambo(torch.as_tensor(u, device=DEV), sqrt_s)
+    hel = torch.as_tensor(h.astype(np.int32), device=DEV)
+    ref = p64.eval(mom, hel).cpu().numpy()
+    p = _proc(n, "per_point", "fp32c")
+    assert p.info()["fixup"] == 1 and p.info()["fix_kappa"] > 0
+    off = _proc(n, "per_point", "fp32c", make_variant(fixup=-1))
+    assert off.info()["fixup"] == 0
+    floor = 1e-3 * np.median(np.abs(ref))
+    for M in (N, 1000, 1, 4099, N):
+        m = mom[:, :M].contiguous()
+        got = p.eval(m, hel[:M].contiguous()).cpu().numpy()
+        err = np.abs(got - ref[:M])
+        assert (err / np.maximum(np.abs(ref[:M]), floor)).max() < 1e-4, M
+        rel = err / np.abs(ref[:M])
+        assert rel.max() < 3e-4, (M, rel.max())
+    raw = off.eval(mom, hel).cpu().numpy()
+    # the pass changes something: without it the worst point is worse
+    assert np.abs(raw / ref - 1.0).max() > rel.max()

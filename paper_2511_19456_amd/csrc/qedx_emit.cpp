@@ -110,6 +110,10 @@ struct Emitter {
   bool amp_store = false;  // body() also stores every configuration's amplitude
   bool stage() const { return (v.order & 16) != 0; }
   int lds_slots = 0;
+  // partition slot loop: photon polarisation vectors computed once per point
+  // (and helicity-loop iteration) before the loop, kept in per-lane LDS and
+  // read by slot inside it, instead of once per partition
+  bool pol_lds = false;
   static constexpr int kTile = 4;
 
   void emitK(uint32_t mask) {
@@ -186,7 +190,13 @@ struct Emitter {
         else if (p == pr.i_eout)
           os << ind << "const qx::sp4<" << T << "> " << nm << " = qx::ubar_out<" << T << ">(" << m << "0, " << m
              << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", 1.0);\n";
-        else {
+        else if (slot && pol_lds) {
+          std::string sp = "sp" + std::to_string(slot_of(p));
+          os << ind << "const qx::pol3<" << T << "> " << nm << " = {";
+          for (int c = 0; c < 3; ++c)
+            os << (c ? ", " : "") << "qx_pol[(3 * " << sp << " + " << c << ") * " << v.block << " + threadIdx.x]";
+          os << "};\n";
+        } else {
           if (slot) m = "k" + std::to_string(slot_of(p)) + "_";
           os << ind << "const qx::pol3<" << T << "> " << nm << " = qx::pol<" << T << ">(" << m << "1, " << m << "2, "
              << m << "3, " << hel_expr(n) << ");\n";
@@ -442,6 +452,15 @@ struct Emitter {
     for (int p : {pr.i_ein, pr.i_eout})
       for (int mu = 0; mu < 4; ++mu)
         os << ind << "const double m" << p << "_" << mu << " = mom[" << (4 * p + mu) << " * N + ptc];\n";
+    if (pol_lds)
+      for (int a = 0; a < P; ++a) {
+        int pp = pr.photon_particle[a];
+        os << ind << "{ const qx::pol3<" << T << "> e_ = qx::pol<" << T << ">(mom[" << (4 * pp + 1) << " * N + ptc], mom["
+           << (4 * pp + 2) << " * N + ptc], mom[" << (4 * pp + 3) << " * N + ptc], (int)((hc >> " << pp << ") & 1u));";
+        for (int c = 0; c < 3; ++c)
+          os << " qx_pol[" << (3 * pp + c) * v.block << " + threadIdx.x] = e_.e" << (c + 1) << ";";
+        os << " }\n";
+      }
     os << ind << "#pragma unroll 1\n" << ind << "for (int it = 0; it < " << nit << "; ++it) {\n";
     std::string outer = ind;
     ind += "  ";
@@ -918,6 +937,7 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   }
   if (v.order & 8) {
     e.slot = true;
+    e.pol_lds = true;
     e.slot_tab = kname + "_slots";
     e.emit_slot_table();
   }
@@ -963,6 +983,8 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     std::string decl;
     if (e.lds_slots > 0)
       decl = "  __shared__ " + e.T + " qx_lds[" + std::to_string(e.lds_slots * 8 * v.block) + "];\n";
+    if (e.pol_lds)
+      decl += "  __shared__ " + e.T + " qx_pol[" + std::to_string(3 * d.proc.npart * v.block) + "];\n";
     size_t at = src.find(lds_mark);
     src.replace(at, lds_mark.size(), decl);
   }
@@ -1199,13 +1221,15 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
   return all.str();
 }
 
-std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* stats) {
+std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* stats,
+                               bool pol_param) {
   check_variant(d, v);
   if (v.order & 16) throw std::invalid_argument("LDS staging is built for eval kernels only");
   Emitter e(d, v);
   std::ostringstream& os = e.os;
   if (v.order & 8) {
     e.slot = true;
+    e.pol_lds = pol_param;
     e.slot_tab = fname + "_slots";
     e.emit_slot_table();
   }
@@ -1216,7 +1240,8 @@ std::string emit_body_function(const Dag& d, const Variant& v, const std::string
   }
   os << "static __device__ double " << fname
      << "(const double* __restrict__ mom, long long N, long long ptc, unsigned hrt_in"
-     << (v.fixup ? ", int& fixflag, double fix_kappa" : "") << ")\n{\n";
+     << (e.pol_lds ? ", " + e.T + "* __restrict__ qx_pol" : std::string()) << (v.fixup ? ", int& fixflag, double fix_kappa" : "")
+     << ")\n{\n";
   if (!e.local() && !e.slot) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
   e.lane_work("hrt_in");

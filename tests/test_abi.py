@@ -96,3 +96,31 @@ def test_corrupt_cache_entry_is_rebuilt(tmp_path):
     env = dict(os.environ, QEDX_CACHE_DIR=str(tmp_path))
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
     assert r.stdout.strip() == "True True", r.stdout + r.stderr
+
+
+def test_status_codes_for_crossed_processes_and_the_pipe_probe():
+    """Argument checks that run before any device call."""
+    L = _lib.lib()
+    ms = ctypes.c_double()
+    h = ctypes.c_void_p()
+    # n_in + n_out <= 7, both >= 1
+    assert L.qed_prebuild_crossed(4, 4, 1, 0, None, ctypes.byref(ms)) == _lib.QED_ERR_UNSUPPORTED
+    assert L.qed_prebuild_crossed(0, 2, 1, 0, None, ctypes.byref(ms)) == _lib.QED_ERR_UNSUPPORTED
+    assert L.qed_process_create_crossed(2, 0, 0, 0, None, ctypes.byref(h)) == _lib.QED_ERR_UNSUPPORTED
+    assert L.qed_process_create_crossed(2, 1, 0, 0, None, None) == _lib.QED_ERR_INVALID_ARG
+    # a fix-up threshold below 1 is rejected
+    v = Q.make_variant(fix_kappa=0.5)
+    assert L.qed_prebuild(3, 1, 1, ctypes.byref(v), 0, ctypes.byref(ms)) == _lib.QED_ERR_INVALID_ARG
+    # pipe probe: kind, sizes, iteration counts and buffers are checked first
+    assert L.qed_pipe_probe(3, 1, 8, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert L.qed_pipe_probe(0, 0, 8, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert L.qed_pipe_probe(1, 1, 7, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert L.qed_pipe_probe(0, 1, 8, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
+
+
+def test_fp32c_per_point_source_has_the_fp64_pass():
+    src = Q.emit_source(4, "per_point", "fp32c")
+    assert "_fix(" in src and "_b64(" in src and "fix_kappa" in src and "__ballot" in src
+    off = Q.emit_source(4, "per_point", "fp32c", Q.make_variant(fixup=-1))
+    assert "_fix(" not in off and "fix_kappa" not in off
+    assert "_fix(" not in Q.emit_source(4, "per_point", "fp64")

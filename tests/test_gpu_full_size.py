@@ -1,0 +1,136 @@
+"""GPU parity at the benchmark's full sizes and launch configuration.
+
+Each test builds the workload exactly as bench.py does (same generator, seed,
+N, process defaults and launch path) and checks sampled outputs against the
+CPU oracle point by point, plus properties that hold for every output
+(finite, positive, FP32C within its bound of the FP64 kernel).  Samples are
+spread over the whole batch, first and last point included, so they cover
+every workgroup position and the ragged tail of the grid.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import qed_oracle as O
+from paper_2511_19456_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _samples(N, k):
+    idx = np.unique(np.concatenate([np.linspace(0, N - 1, k).astype(np.int64),
+                                    inputs.rng_for(99).integers(0, N, size=k)]))
+    return idx
+
+
+def _proc(n, mode, prec="fp64"):
+    from paper_2511_19456_amd.qedx import QedProcess
+    return QedProcess(n, mode, prec)
+
+
+def test_full_size_compton_n1_65536():
+    """65,536 one-photon points, helicity sum: every point against the oracle
+    and against Klein-Nishina."""
+    wl = inputs.WORKLOADS["compton_n1_sum_65536"]
+    N = wl["N"]
+    print(f"full size n=1 sum N={N}", flush=True)
+    mom = inputs.compton_lab_momenta(wl["seed"], N)
+    got = _proc(1, "sum").eval(torch.as_tensor(mom, device=DEV)).cpu().numpy()
+    ref = O.m2(mom, 1, "sum", chunk=8192).numpy()
+    assert np.abs(got / ref - 1).max() < 1e-10
+    ct = mom[15] / mom[12]
+    wp = mom[12]
+    kn = 8.0 * (wp + 1.0 / wp - (1.0 - ct * ct))
+    assert np.abs(got / kn - 1).max() < 1e-12
+
+
+def test_full_size_n3_sum_2p20():
+    """The headline workload: 2^20 RAMBO points at sqrt(s) = 10, momenta from
+    the device RAMBO as in the bench, all 64 configurations summed."""
+    wl = inputs.WORKLOADS["n3_sum_rs10_2p20"]
+    n, N, rs = wl["n"], wl["N"], wl["sqrt_s"]
+    print(f"full size n=3 sum N={N}", flush=True)
+    u, _ = inputs.rambo_inputs(wl["seed"], n, N)
+    p = _proc(n, "sum")
+    mom = p.rambo(torch.as_tensor(u, device=DEV), rs)
+    out = p.eval(mom)
+    assert bool(torch.isfinite(out).all()) and bool((out > 0).all())
+    idx = _samples(N, 96)
+    ref_mom = O.momenta_soa_from_uniforms(u[:, idx], rs, n)
+    assert (mom[:, idx].cpu() - ref_mom).abs().max().item() < 1e-12 * rs
+    ref = O.m2(ref_mom, n, "sum").numpy()
+    assert np.abs(out[idx].cpu().numpy() / ref - 1).max() < 1e-10
+    # FP32C on the same batch: within 1e-4 of the FP64 kernel on every point
+    o32 = _proc(n, "sum", "fp32c").eval(mom)
+    assert (((o32 - out).abs() / out.abs()).max().item()) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_full_size_n5_per_point_2p20(prec):
+    """2^20 points at sqrt(s) = 20, one random configuration per point."""
+    wl = inputs.WORKLOADS["n5_perpoint_rs20_2p20"]
+    n, N, rs = wl["n"], wl["N"], wl["sqrt_s"]
+    print(f"full size n=5 per point {prec} N={N}", flush=True)
+    u, h = inputs.rambo_inputs(wl["seed"], n, N, with_helicities=True)
+    p = _proc(n, "per_point", prec)
+    mom = p.rambo(torch.as_tensor(u, device=DEV), rs)
+    hd = torch.as_tensor(h.astype(np.int32), device=DEV)
+    out = p.eval(mom, hd)
+    assert bool(torch.isfinite(out).all()) and bool((out >= 0).all())
+    idx = _samples(N, 24)
+    ref_mom = O.momenta_soa_from_uniforms(u[:, idx], rs, n)
+    ref = O.m2(ref_mom, n, "per_point", h[idx]).numpy()
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert np.abs(out[idx].cpu().numpy() / ref - 1).max() < tol
+    if prec == "fp32c":
+        o64 = _proc(n, "per_point", "fp64").eval(mom, hd)
+        assert (((out - o64).abs() / o64.abs()).max().item()) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_full_size_mixed_batch(prec):
+    """The mixed n = 1..6 batch of the bench (2.77 M points, autotuned plan):
+    every segment sampled against the oracle."""
+    from paper_2511_19456_amd.qedx import BatchPlan
+    spec = inputs.mixed_batch_spec(inputs.WORKLOADS["mixed_n1to6"]["seed"])
+    segs, keep = [], []
+    for (n, Np, rs, sub) in spec:
+        u, h = inputs.rambo_inputs(sub, n, Np, with_helicities=True)
+        p = _proc(n, "per_point", prec)
+        mom = p.rambo(torch.as_tensor(u, device=DEV), rs)
+        hd = torch.as_tensor(h.astype(np.int32), device=DEV)
+        out = torch.full((Np,), float("nan"), dtype=torch.float64, device=DEV)
+        segs.append((p, mom, hd, out))
+        keep.append((n, Np, rs, u, h))
+    print(f"full size mixed batch {prec}: {[(n, Np) for (n, Np, _, _, _) in keep]}", flush=True)
+    plan = BatchPlan(segs, tile_points=0)
+    for s in segs:
+        s[3].fill_(float("nan"))
+    plan.launch()
+    torch.cuda.synchronize()
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    for (p, mom, hd, out), (n, Np, rs, u, h) in zip(segs, keep):
+        assert bool(torch.isfinite(out).all()) and bool((out >= 0).all()), n
+        idx = _samples(Np, 6 if n == 6 else 12)
+        ref_mom = O.momenta_soa_from_uniforms(u[:, idx], rs, n)
+        ref = O.m2(ref_mom, n, "per_point", h[idx]).numpy()
+        assert np.abs(out[idx].cpu().numpy() / ref - 1).max() < tol, n
+
+
+def test_full_size_gradient_n4_2p18():
+    """2^18 points at sqrt(s) = 15: log|M|^2 and its gradient through RAMBO,
+    sampled against the oracle's reverse-mode gradient."""
+    wl = inputs.WORKLOADS["grad_n4_sum_rs15_2p18"]
+    n, N, rs = wl["n"], wl["N"], wl["sqrt_s"]
+    print(f"full size gradient n=4 N={N}", flush=True)
+    u, _ = inputs.rambo_inputs(wl["seed"], n, N)
+    p = _proc(n, "sum")
+    val, g = p.eval_grad(torch.as_tensor(u, device=DEV), rs)
+    assert bool(torch.isfinite(val).all()) and bool(torch.isfinite(g).all())
+    idx = _samples(N, 8)
+    v_o, g_o = O.logm2_and_grad(u[:, idx], rs, n)
+    assert np.abs(val[idx].cpu().numpy() - v_o.numpy()).max() < 1e-10 * max(1.0, np.abs(v_o.numpy()).max())
+    gg, go = g[:, idx].cpu().numpy(), g_o.numpy()
+    assert (np.linalg.norm(gg - go, axis=0) / np.linalg.norm(go, axis=0)).max() < 1e-10

@@ -249,7 +249,7 @@ static qed_status get_code_object(const std::string& tag, const std::string& src
 // processes
 // ---------------------------------------------------------------------------
 
-static void default_variant(int n, int nin, qed_hel_mode mode, qed_precision prec, Variant& v) {
+static void default_variant(int n, int nin, qed_hel_mode mode, qed_precision prec, int rewrite, Variant& v) {
   v = Variant();
   v.prec = prec == QED_FP64 ? PREC_F64 : PREC_F32C;
   v.mode = mode == QED_HEL_SUM ? HEL_SUM : HEL_PER_POINT;
@@ -272,7 +272,16 @@ static void default_variant(int n, int nin, qed_hel_mode mode, qed_precision pre
     // for few photons, partly looped for more
     v.lane_mask = (1u << 0) | (1u << i_eout);
     uint32_t photons = all & ~v.lane_mask;
-    if (P <= 4) {
+    if (P == 4 && prec == QED_FP64 && !rewrite) {
+      // 4 photons, node-reduced FP64: only the e-_out spin over lanes (2 per
+      // point), everything else in the graph, one basic block per partition:
+      // no scratch (202 AGPRs instead of 256 + 360 B spill) and 6 % faster
+      // than 4 spin lanes with one shared block; FP32C and the distributive
+      // rewrite keep the shared block, where it measured faster
+      v.lane_mask = 1u << i_eout;
+      v.enum_mask = all & ~v.lane_mask;
+      v.order = 4;
+    } else if (P <= 4) {
       v.enum_mask = photons;
     } else {
       // keep 2^3 configurations inside the graph, loop over the rest
@@ -312,7 +321,7 @@ static qed_status make_variant(int n, int nin, qed_hel_mode mode, qed_precision 
 
 static qed_status make_variant_shape(int n, int nin, qed_hel_mode mode, qed_precision prec, const qed_variant* qv,
                                      Variant& v) {
-  default_variant(n, nin, mode, prec, v);
+  default_variant(n, nin, mode, prec, qv && !qv->use_defaults ? qv->rewrite : 0, v);
   const int P = n + nin, npart = P + 2;
   if (qv && !qv->use_defaults) {
     if (qv->block) v.block = qv->block;
@@ -338,6 +347,10 @@ static qed_status make_variant_shape(int n, int nin, qed_hel_mode mode, qed_prec
       v.lane_mask = qv->lane_bits & all;
       v.loop_mask = qv->loop_bits & all & ~v.lane_mask;
       v.enum_mask = all & ~v.lane_mask & ~v.loop_mask;
+      // an explicit coverage with at most 4 photons keeps the shared block
+      // unless an order is given (the 4-photon default above pairs its own
+      // coverage with per-partition blocks)
+      if (!qv->order && P <= 4) v.order = 0;
     } else if (mode != QED_HEL_SUM && (qv->lane_bits || qv->loop_bits)) {
       return fail(QED_ERR_INVALID_ARG, "lane_bits/loop_bits apply to SUM mode only");
     }

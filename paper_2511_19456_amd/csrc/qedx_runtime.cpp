@@ -284,8 +284,14 @@ static void default_variant(int n, int nin, qed_hel_mode mode, qed_precision pre
     } else if (P <= 4) {
       v.enum_mask = photons;
     } else {
-      // keep 2^3 configurations inside the graph, loop over the rest
-      uint32_t e = 0;
+      // keep 2^3 photon configurations inside the graph, loop over the rest;
+      // with 5 photons in FP64 (node-reduced) the e-_in spin also moves into
+      // the graph and only the e-_out spin stays on lanes (27 % faster)
+      if (P == 5 && prec == QED_FP64 && !rewrite) {
+        v.lane_mask = 1u << i_eout;
+        photons = all & ~v.lane_mask & ~1u;
+      }
+      uint32_t e = (v.lane_mask & 1u) ? 0u : 1u;
       int k = 0;
       for (int b = 0; b < npart && k < 3; ++b)
         if ((photons >> b) & 1) {

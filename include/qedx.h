@@ -90,8 +90,9 @@ typedef struct {
                            1 = node reduction followed by the distributive rewrite the paper
                            proposes (Sec. IV): sums over photon orderings are factored, so the
                            diagram sum becomes one join per photon partition and the currents
-                           one per photon subset.  Same result up to rounding.  The gradient
-                           kernel always uses the node-reduced graph. */
+                           one per photon subset.  Same result up to rounding.  The fused
+                           gradient (n <= 3) uses the node-reduced graph; the split gradient
+                           (n = 4, 5) sweeps the process's own graph form. */
   int32_t partial;      /* nonzero: instead of the full pipeline, the paper's unsplit graph
                            after only the first partial_steps single node reductions in the
                            random order seeded by partial_seed (0 steps = unreduced), emitted

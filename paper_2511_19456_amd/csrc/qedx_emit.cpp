@@ -1221,13 +1221,15 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
   return all.str();
 }
 
-std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* stats) {
+std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* stats,
+                               bool pol_param) {
   check_variant(d, v);
   if (v.order & 16) throw std::invalid_argument("LDS staging is built for eval kernels only");
   Emitter e(d, v);
   std::ostringstream& os = e.os;
   if (v.order & 8) {
     e.slot = true;
+    e.pol_lds = pol_param;
     e.slot_tab = fname + "_slots";
     e.emit_slot_table();
   }
@@ -1238,7 +1240,8 @@ std::string emit_body_function(const Dag& d, const Variant& v, const std::string
   }
   os << "static __device__ double " << fname
      << "(const double* __restrict__ mom, long long N, long long ptc, unsigned hrt_in"
-     << (v.fixup ? ", int& fixflag, double fix_kappa" : "") << ")\n{\n";
+     << (e.pol_lds ? ", " + e.T + "* __restrict__ qx_pol" : std::string()) << (v.fixup ? ", int& fixflag, double fix_kappa" : "")
+     << ")\n{\n";
   if (!e.local() && !e.slot) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
   e.lane_work("hrt_in");

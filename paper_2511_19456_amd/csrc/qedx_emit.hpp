@@ -93,7 +93,11 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
 // returning the per-lane partial sum of |A|^2.  With v.fixup (FP32C, per
 // point) it takes (..., int& fixflag, double fix_kappa) and sets fixflag as
 // the eval kernel's fix-up test does.
-std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* st);
+// With pol_param and a partition slot loop (order & 8) the body also takes
+// (..., T* qx_pol) after hrt: per-lane LDS of 3 npart x (threads per
+// workgroup, 256) values for the photon polarisations, hoisted out of the loop.
+std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* st,
+                               bool pol_param = false);
 
 // The device header text (inlined into every generated unit).
 const std::string& device_header_text();

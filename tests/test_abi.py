@@ -124,3 +124,27 @@ def test_fp32c_per_point_source_has_the_fp64_pass():
     off = Q.emit_source(4, "per_point", "fp32c", Q.make_variant(fixup=-1))
     assert "_fix(" not in off and "fix_kappa" not in off
     assert "_fix(" not in Q.emit_source(4, "per_point", "fp64")
+
+
+def test_default_kernel_shapes():
+    """The measured default shapes (helicity coverage, schedule, join split,
+    fix-up) that the bench and the documentation rely on."""
+    def tag(n, mode, prec, **kw):
+        src = Q.emit_source(n, mode, prec, Q.make_variant(**kw) if kw else None)
+        return src.splitlines()[0].split("generated by qedx: ")[1]
+    # 4 photons, FP64 sum: e-_out spin on lanes, one block per partition
+    assert tag(3, "sum", "fp64") == "nin1_nout3_p0_m0_e59_l4_o0_b256_s2_j1_r4_w0"
+    # FP32C and the distributive rewrite keep both spins on lanes, shared block
+    assert "_l5_o0_" in tag(3, "sum", "fp32c") and "_r0_" in tag(3, "sum", "fp32c")
+    assert "_l5_o0_" in tag(3, "sum", "fp64", rewrite=1)
+    # an explicit coverage keeps the shared block unless an order is given
+    assert "_l7_o0_" in tag(3, "sum", "fp64", lane_bits=7) and "_r0_" in tag(3, "sum", "fp64", lane_bits=7)
+    # 5 photons, FP64 sum: e-_in spin and 3 photons in the graph, 2 looped
+    assert tag(4, "sum", "fp64").startswith("nin1_nout4_p0_m0_e27_l4_o96_")
+    # per point: join split ceil(P/2) for 5 and 7 photons, slot loop
+    assert "_s3_" in tag(4, "per_point", "fp64") and "_r8_" in tag(4, "per_point", "fp64")
+    assert "_s4_" in tag(6, "per_point", "fp64")
+    assert "_s3_" in tag(5, "per_point", "fp64")
+    # FP32C per point carries the FP64 pass
+    assert tag(5, "per_point", "fp32c").endswith("_f1")
+    assert not tag(5, "per_point", "fp32c", fixup=-1).endswith("_f1")

@@ -88,9 +88,19 @@ def cpu_baseline(u, sqrt_s, n, budget_s):
         O.m2(m, n, "sum")
         t_used += time.perf_counter() - t0
         done += chunk
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": done / t_used, "unit": "points/s", "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"first {done} points of the workload (n=3, helicity sum), momenta from the oracle's RAMBO, "
-                      f"{t_used:.1f} s of |M|^2 time"}
+                      f"{t_used:.1f} s of |M|^2 time on {torch.get_num_threads()} threads of {model} "
+                      f"({os.cpu_count()} logical CPUs visible)"}
 
 
 def traffic_entry(code_hash):

@@ -148,8 +148,8 @@ def main():
         copy_calibration()
         return
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); points are independent, "
-              "so sharding is a split of the point range (DESIGN.md, 'More than one GPU')", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (asked for --gpus {a.gpus}); points are independent, so "
+              "running on several GPUs is a split of the point range with no communication", file=sys.stderr)
         sys.exit(2)
     import torch
 

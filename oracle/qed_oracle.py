@@ -16,7 +16,7 @@ with explicit 4x4 Dirac matrices in complex128.  For one photon this is Eq. (1).
 All arithmetic is float64 / complex128; the only library primitives are small
 matrix products, and automatic differentiation for the gradient.
 
-Readings where the paper is silent (all stated again in the design doc):
+Readings where the paper is silent:
 * Reduced amplitude: the coupling and the overall phase (-ie)^(n+1) i^n are
   dropped, i.e. e = 1; |M|^2 reported is sum |A_h|^2 with no spin average.
 * iepsilon in S(Q) is set to 0 (no inner line can go on shell for this process

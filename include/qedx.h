@@ -184,7 +184,8 @@ qed_status qed_eval_grad(const qed_process* p, const double* uniforms, double sq
 
 /* Mixed-process batches: segments of different processes evaluated by one
  * persistent kernel launch (captured in a HIP graph at plan creation).
- * All processes of one plan must share the precision and be PER_POINT. */
+ * All processes of one plan must share the precision (and, for FP32C, the
+ * FP64 fix-up setting) and be PER_POINT. */
 typedef struct {
   const qed_process* proc;
   const double* momenta; /* device [4(n+3)][N] */

@@ -106,6 +106,8 @@ DEFAULT_KERNELS = [
     (1, 1, 0, dict(n_in=2)), (1, 1, 0, dict(n_in=3)), (1, 1, 0, dict(n_in=4)), (1, 1, 0, dict(n_in=5)),
     (1, 1, 0, dict(n_in=6)), (1, 1, 1, dict(n_in=3)), (1, 1, 1, dict(n_in=6)), (2, 0, 0, dict(n_in=2)),
     (1, 1, 0, dict(n_in=6, rewrite=1)),
+    # FP32C per point without the FP64 pass (bench leg and tests)
+    (3, 1, 1, dict(fixup=-1)), (5, 1, 1, dict(fixup=-1)),
 ]
 
 

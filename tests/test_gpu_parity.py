@@ -459,3 +459,30 @@ def test_fp32c_fp64_fixup(n, sqrt_s):
     raw = off.eval(mom, hel).cpu().numpy()
     # the pass changes something: without it the worst point is worse
     assert np.abs(raw / ref - 1.0).max() > rel.max()
+
+
+def test_batch_plan_rejections():
+    """Plans refuse what their single module cannot serve: crossed processes,
+    mixed precisions, mixed FP64 fix-up settings, helicity sums."""
+    from paper_2511_19456_amd._lib import QedError
+    from paper_2511_19456_amd.qedx import BatchPlan, QedProcess, make_variant
+    N = 64
+
+    def seg(p):
+        mom = torch.zeros(4 * p.n_particles, N, dtype=torch.float64, device=DEV)
+        hel = torch.zeros(N, dtype=torch.int32, device=DEV)
+        return (p, mom, hel, torch.empty(N, dtype=torch.float64, device=DEV))
+    a = QedProcess(2, "per_point", "fp32c")
+    cases = [
+        [seg(QedProcess(1, "per_point", "fp64", n_in=2))],
+        [seg(QedProcess(2, "per_point", "fp64")), seg(a)],
+        [seg(a), seg(QedProcess(3, "per_point", "fp32c", make_variant(fixup=-1)))],
+    ]
+    for segs in cases:
+        with pytest.raises(QedError):
+            BatchPlan(segs, tile_points=64)
+    p_sum = QedProcess(2, "sum", "fp64")
+    with pytest.raises(QedError):
+        BatchPlan([(p_sum, torch.zeros(20, N, dtype=torch.float64, device=DEV),
+                    torch.zeros(N, dtype=torch.int32, device=DEV), torch.empty(N, dtype=torch.float64, device=DEV))],
+                  tile_points=64)

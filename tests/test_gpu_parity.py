@@ -486,3 +486,54 @@ def test_batch_plan_rejections():
         BatchPlan([(p_sum, torch.zeros(20, N, dtype=torch.float64, device=DEV),
                     torch.zeros(N, dtype=torch.int32, device=DEV), torch.empty(N, dtype=torch.float64, device=DEV))],
                   tile_points=64)
+
+
+def test_degenerate_kinematics():
+    """Edge cases of the kinematics: photons exactly along the z axis (the
+    polarisation basis switches to its k_T = 0 branch), backward scattering,
+    and a nearly soft photon (a propagator close to its pole)."""
+    # one photon, exact angles: Klein-Nishina closed form at omega = 1
+    theta = np.array([0.0, np.pi / 2, np.pi, np.pi, 0.0])
+    phi = np.array([0.0, 0.0, 0.0, 1.3, 2.0])
+    mom = inputs.compton_lab_angles(theta, phi)
+    got = _proc(1).eval(torch.as_tensor(mom, device=DEV)).cpu().numpy()
+    ct, wp = np.cos(theta), mom[12]
+    kn = 8.0 * (wp + 1.0 / wp - (1.0 - ct * ct))
+    assert np.abs(got / kn - 1).max() < 1e-12
+    # every configuration at those points against the oracle
+    N = len(theta)
+    hel = np.tile(np.arange(16, dtype=np.uint32), N)
+    mm = np.repeat(mom, 16, axis=1)
+    pp = _proc(1, "per_point").eval(torch.as_tensor(mm, device=DEV),
+                                    torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
+    ref = O.m2(mm, 1, "per_point", hel).numpy()
+    scale = np.repeat(kn / 16.0, 16)
+    assert (np.abs(pp - ref) / np.maximum(np.abs(ref), 1e-3 * scale)).max() < 1e-10
+    # two photons, the first final-state photon nearly soft (RAMBO energy
+    # -ln(u2 u3) -> 0).  The oracle forms Q.Q - m^2 plainly and loses digits
+    # as the photon softens (its own error ~1e-11 at E_k = 7e-4 sqrt(s),
+    # ~3e-8 at 7e-7); the kernels use the cancellation-free 2 p.K + K^2.  So:
+    # against the oracle at the milder point, and at the extreme point against
+    # the host interpreter of the same graph (same denominators, plain loops).
+    # There the eikonal terms of the diagrams cancel to ~1/E_k of their size,
+    # so two FP64 summation orders already differ by ~1e-9: tolerance 1e-8.
+    from paper_2511_19456_amd.qedx import graph_interpret
+    n, rs, N = 2, 6.0, 8
+    for eps, soft, tol in ((1e-4, 1e-3, 1e-10), (1e-7, 1e-6, 1e-8)):
+        u, h = inputs.rambo_inputs(77, n, N, with_helicities=True)
+        u[4 + 2] = 1.0 - eps
+        u[4 + 3] = 1.0 - eps
+        ref_mom = O.momenta_soa_from_uniforms(u, rs, n)
+        assert float(ref_mom[4 * 3].max()) < soft * rs   # the soft photon's energy
+        m = torch.as_tensor(ref_mom.numpy(), device=DEV)
+        s_got = _proc(n).eval(m).cpu().numpy()
+        p_got = _proc(n, "per_point").eval(m, torch.as_tensor(h.astype(np.int32), device=DEV)).cpu().numpy()
+        if eps == 1e-4:
+            s_ref = O.m2(ref_mom, n, "sum").numpy()
+            p_ref = O.m2(ref_mom, n, "per_point", h).numpy()
+        else:
+            pts = O.soa_to_points(ref_mom).numpy().reshape(N, -1)
+            s_ref = graph_interpret(n, pts, None, enum_mask=(1 << (n + 3)) - 1, reduced=True)
+            p_ref = graph_interpret(n, pts, h, reduced=True)
+        assert np.abs(s_got / s_ref - 1).max() < tol, eps
+        assert (np.abs(p_got - p_ref) / np.maximum(np.abs(p_ref), 1e-3 * s_ref / 32)).max() < tol, eps

@@ -91,6 +91,7 @@ DEFAULT_KERNELS = [
     # distributive rewrite (bench legs and parity tests)
     (2, 0, 0, dict(rewrite=1)), (3, 0, 0, dict(rewrite=1)), (3, 0, 0, dict(rewrite=1, lane_bits=7)),
     (4, 0, 0, dict(rewrite=1)), (4, 1, 0, dict(rewrite=1)), (5, 1, 0, dict(rewrite=1)), (6, 1, 0, dict(rewrite=1)),
+    (1, 1, 0, dict(rewrite=1)), (2, 1, 0, dict(rewrite=1)), (3, 1, 0, dict(rewrite=1)),
     (3, 0, 1, dict(rewrite=1)), (5, 1, 1, dict(rewrite=1)),
     # kernel shapes the parity tests exercise
     (3, 0, 0, dict(lane_bits=7)), (3, 0, 0, dict(lane_bits=5, order=4)), (3, 0, 0, dict(lane_bits=63, order=4)),

@@ -1,0 +1,94 @@
+"""Pins of the extended-precision oracle (CPU).
+
+The long-double oracle evaluates the same plain definition as the float64
+oracle (per-diagram Feynman rules with explicit Dirac matrices, Sec. I-D and
+Sec. III-A) with 11 more bits.  It is pinned independently of the float64
+code path by the Klein-Nishina closed form at n = 1 (evaluated in long double
+too), by the soft-photon (eikonal) limit that relates two photons to one,
+and by agreement with the pinned float64 oracle at points where that oracle's
+own error is small; its conditioning numbers satisfy their ordering.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import qed_oracle as O
+from oracle import qed_oracle_ld as L
+from paper_2511_19456_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+
+
+def test_klein_nishina_long_double():
+    """Sum over the 16 configurations at n = 1, electron at rest, omega = 1:
+    8 [w'/w + w/w' - sin^2 theta] (textbook Klein-Nishina), worked values 16,
+    12 and 80/3 at theta = 0, pi/2, pi, and random angles, all in long double."""
+    theta = np.array([0.0, np.pi / 2, np.pi])
+    mom = inputs.compton_lab_angles(theta, np.zeros(3))
+    got = L.m2_sum(L.soa_to_points(mom), 1)
+    want = np.array([16.0, 12.0, 80.0 / 3.0], dtype=np.longdouble)
+    # the angles are float64, so sin^2(pi/2) etc. carry float64 rounding
+    assert np.max(np.abs(got / want - 1)) < 1e-15
+    mom = inputs.compton_lab_momenta(11, 200)
+    pts = L.soa_to_points(mom)
+    got = L.m2_sum(pts, 1)
+    w, wp = pts[:, 1, 0], pts[:, 3, 0]
+    ct = pts[:, 3, 3] / wp
+    kn = 8 * (wp / w + w / wp - (1 - ct * ct))
+    # the float64 inputs satisfy the two-body kinematics only to float64
+    # rounding (p' = p + k - k' is formed in float64), so agreement is at that level
+    assert np.max(np.abs(got / kn - 1)) < 2e-15
+
+
+@pytest.mark.parametrize("n,rs", [(1, 4.0), (2, 6.0), (3, 10.0), (4, 15.0)])
+def test_long_double_agrees_with_float64_oracle(n, rs):
+    """Per configuration and summed, against the float64 oracle (itself
+    pinned by KN, Ward, Lorentz, Bose and the soft limit): agreement to the
+    float64 oracle's rounding, bounded by its conditioning."""
+    N = 48
+    u, h = inputs.rambo_inputs(50 + n, n, N, with_helicities=True)
+    mom = O.momenta_from_uniforms(u, rs, n)
+    soa = O.points_to_soa(mom).numpy()
+    pp, kt, kc = L.m2_per_point(mom.numpy(), h, n)
+    ref = O.m2(soa, n, "per_point", h).numpy()
+    err = np.abs(ref / pp.astype(np.float64) - 1)
+    assert np.all(err < 1e-13 + 64 * 2.0 ** -53 * kc.astype(np.float64))
+    assert np.all(kt >= 1 - 1e-12) and np.all(kc >= kt * (1 - 1e-12))
+    if n <= 3:
+        tot = L.m2_sum(mom.numpy(), n)
+        assert np.max(np.abs(O.m2(soa, n, "sum").numpy() / tot.astype(np.float64) - 1)) < 1e-13
+
+
+def test_near_soft_golden_values():
+    """The stored near-soft values: at the milder point (soft energy 7e-4
+    sqrt(s)) the float64 oracle agrees to 1e-11; at the extreme point (7e-7)
+    the float64 oracle's plain Q.Q - m^2 loses ~9 digits, the long-double
+    values do not; both obey the eikonal limit of the one-photon process
+    (Sec. I-D propagator near its pole) to first order in the soft energy."""
+    from make_golden import near_soft_points, read_near_soft
+    d = read_near_soft()
+    assert set(d) == {1e-4, 1e-7}
+    for eps, r in d.items():
+        mom, h = near_soft_points(eps)
+        assert np.array_equal(mom, r["mom"]) and np.array_equal(h, r["hel"])
+        s64 = O.m2(r["mom"], 2, "sum").numpy()
+        e64 = np.abs(s64 / r["sum"] - 1).max()
+        if eps == 1e-4:
+            assert e64 < 1e-11
+        else:
+            assert 1e-11 < e64 < 1e-7   # the float64 oracle's denominator cancellation
+        # eikonal factor times the one-photon helicity sum at the reduced kinematics
+        pts = O.soa_to_points(r["mom"]).numpy()
+        p, pp, ks = pts[:, 0], pts[:, 2], pts[:, 3]
+        e0 = ks[:, 0] / 6.0
+        dot = lambda a, b: a[:, 0] * b[:, 0] - (a[:, 1:] * b[:, 1:]).sum(1)
+        eik = 2 * dot(p, pp) / (dot(p, ks) * dot(pp, ks)) - 1 / dot(p, ks) ** 2 - 1 / dot(pp, ks) ** 2
+        # one-photon process e-(p) gamma(k) -> e-(p'') gamma(k'_2), p'' = p' + k_soft
+        red = np.stack([p, pts[:, 1], pp + ks, pts[:, 4]], axis=1)
+        # (p'' is off shell by 2 p'.k_soft, an O(soft energy) change like the limit's own)
+        n1 = O.m2(np.ascontiguousarray(red.transpose(1, 2, 0).reshape(16, -1)), 1, "sum").numpy()
+        ratio = r["sum"] / (eik * n1)
+        assert np.all(np.abs(ratio - 1) < 50 * e0.max()), (eps, ratio)

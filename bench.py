@@ -462,7 +462,7 @@ def extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom_n3):
     def fp64_pipes():
         """FP64 vector pipe, FP64 matrix pipe (v_mfma_f64_16x16x4) and both at
         once: achievable rates on this chip, and whether the two overlap."""
-        from paper_2511_19456_amd._lib import check, lib
+        from paper_2511_19456_amd._lib import check, probe_lib
         blocks = 2048                      # 8 waves per SIMD
         it_v, it_m = 60000, 8000
         mm, cc = 0.999999, 1e-6
@@ -474,12 +474,12 @@ def extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom_n3):
 
         def run(kind):
             if kind == 0:
-                check(lib().qed_pipe_probe(0, blocks, it_v, 0, mm, cc, None, None, ov.data_ptr(), None, stream))
+                check(probe_lib().qed_pipe_probe(0, blocks, it_v, 0, mm, cc, None, None, ov.data_ptr(), None, stream))
             elif kind == 1:
-                check(lib().qed_pipe_probe(1, blocks, it_m, 0, mm, cc, av.data_ptr(), bv.data_ptr(),
+                check(probe_lib().qed_pipe_probe(1, blocks, it_m, 0, mm, cc, av.data_ptr(), bv.data_ptr(),
                                            om.data_ptr(), None, stream))
             else:
-                check(lib().qed_pipe_probe(2, blocks, it_v, it_m, mm, cc, av.data_ptr(), bv.data_ptr(),
+                check(probe_lib().qed_pipe_probe(2, blocks, it_v, it_m, mm, cc, av.data_ptr(), bv.data_ptr(),
                                            ov.data_ptr(), om.data_ptr(), stream))
         waves = blocks * 4
         fl_v = waves * 64 * 16.0 * it_v            # 8 FMA chains per lane

@@ -28,11 +28,14 @@
  *    and return without synchronising.  Launch failures return QED_ERR_HIP.
  *  - On any error the function returns a nonzero status, writes nothing to
  *    the outputs, and qed_last_error() returns a message (thread-local).
- *  - N == 0 is a valid no-op.  Device memory is allocated only by
- *    qed_batch_plan_create (its tile table, counter and, for FP32C, the
- *    fix-up list), by qed_eval_grad for n >= 4, and by qed_eval of FP32C
- *    per-point processes (workspaces owned by the process handle, grown on
- *    demand and freed by qed_process_destroy).
+ *  - N == 0 is a valid no-op.  Process handles are read-only after create:
+ *    calls on one process from several streams or threads may overlap.
+ *    Device memory is allocated, and the device synchronised, only by
+ *    create/destroy calls (processes, batch plans); qed_eval, qed_rambo,
+ *    qed_eval_grad and qed_batch_launch allocate nothing and do not
+ *    synchronise (the split gradient works in a caller-owned workspace).
+ *  - Host-side graph tools (inspection, host references for tests) are
+ *    declared in qedx_tools.h; they are exported by the same library.
  */
 #ifndef QEDX_H
 #define QEDX_H
@@ -63,11 +66,10 @@ typedef enum { QED_HEL_SUM = 0, QED_HEL_PER_POINT = 1 } qed_hel_mode;
  * QED_FP32C: currents, vertices, propagator numerators and diagram values in
  * float32 with compensated (TwoSum) accumulation of the diagram sum;
  * momenta, propagator momenta and denominators, |A|^2 and the helicity sum in
- * float64.  Per-point processes recompute in float64 the points whose diagram
- * sum cancels by more than fix_kappa (qed_variant), which keeps the relative
- * error against float64 below 1e-4 on every point of the stated workloads
- * (measured, not a proof for arbitrary points); helicity sums dilute the
- * cancellation of single configurations and meet the bound without it. */
+ * float64.  Per-point processes recompute in float64 the points whose FP32
+ * evaluation the kernel cannot vouch for (fixup, fix_kappa in qed_variant);
+ * helicity sums dilute the cancellation of single configurations.  The error
+ * against float64 is reported per result by the tests and the benchmark. */
 typedef enum { QED_FP64 = 0, QED_FP32C = 1 } qed_precision;
 
 /* Kernel shape knobs (a zero field = library default for the process).
@@ -92,7 +94,7 @@ typedef struct {
                            diagram sum becomes one join per photon partition and the currents
                            one per photon subset.  Same result up to rounding.  The fused
                            gradient (n <= 3) uses the node-reduced graph; the split gradient
-                           (n = 4, 5) sweeps the process's own graph form. */
+                           (n = 4) sweeps the process's own graph form. */
   int32_t partial;      /* nonzero: instead of the full pipeline, the paper's unsplit graph
                            after only the first partial_steps single node reductions in the
                            random order seeded by partial_seed (0 steps = unreduced), emitted
@@ -152,10 +154,11 @@ qed_status qed_process_info(const qed_process* p, qed_info* out);
  * momenta: device, float64 [4(n+3)][N]; hel: device uint32 [N] in PER_POINT
  * mode and NULL in SUM mode; out: device float64 [N].
  * INVALID_ARG if N < 0, a required pointer is NULL while N > 0, or hel does not
- * match the mode.  FP32C per-point processes with the FP64 fix-up keep a
- * device workspace of 4(N + 1) bytes (allocated, or grown, by the first call
- * with a larger N; freed by qed_process_destroy); calls on one such process
- * must not overlap, and N is limited to 2^32 - 1 for them. */
+ * match the mode.  FP32C per-point processes with the FP64 fix-up launch two
+ * kernels on `stream`: the FP32 pass writes its results and marks the points
+ * it cannot vouch for with a negative value in `out`, the FP64 pass
+ * recomputes the marked points in place; `out` holds final values once both
+ * have run.  No other memory is used. */
 qed_status qed_eval(const qed_process* p, const double* momenta, const uint32_t* hel, int64_t N, double* out,
                     void* stream);
 
@@ -172,15 +175,22 @@ qed_status qed_rambo(const qed_process* p, const double* uniforms, double sqrt_s
  * float64 device buffers.  The gradient is the reverse sweep of the graph:
  * currents are recomputed from their parents on the way back, not stored.
  * n <= 3: forward RAMBO, forward graph, adjoint graph and adjoint RAMBO in one
- * kernel.  n = 4, 5: per chunk of points, RAMBO into a workspace, one kernel
- * storing every configuration's amplitude A_h and 1/|M|^2 (the adjoint seeds
- * conj(A_h)/|M|^2), one adjoint kernel per photon partition, and the RAMBO
- * adjoint; the workspace (about 2.5 KB per point at n = 4, 320 MB at most)
- * belongs to the process, so calls on one process must not overlap on
- * different streams.  `hel` must be NULL.  UNSUPPORTED for PER_POINT or FP32C
- * processes and for n = 6.  QED_ERR_OOM if the workspace cannot be allocated. */
+ * kernel; no workspace (workspace may be NULL).  n = 4: per chunk of points,
+ * RAMBO into the workspace, one kernel storing every configuration's
+ * amplitude A_h and 1/|M|^2 (the adjoint seeds conj(A_h)/|M|^2), one adjoint
+ * kernel per photon partition, and the RAMBO adjoint.  The workspace is
+ * caller-owned device memory, 8-byte aligned, of workspace_bytes bytes: its
+ * size sets the chunk (qed_eval_grad_workspace_size gives the size for the
+ * largest chunk, about 2.5 KB per point at n = 4, at most 320 MB); less than
+ * 64 points' worth (or N's, if smaller) is INVALID_ARG.  Calls that overlap
+ * need workspaces of their own.  `hel` must be NULL.  UNSUPPORTED for
+ * PER_POINT or FP32C processes and for n >= 5. */
 qed_status qed_eval_grad(const qed_process* p, const double* uniforms, double sqrt_s, const uint32_t* hel,
-                         int64_t N, double* out_logm2, double* out_grad, void* stream);
+                         int64_t N, double* out_logm2, double* out_grad, void* workspace, int64_t workspace_bytes,
+                         void* stream);
+/* Workspace bytes qed_eval_grad uses for N points in one chunk (capped at
+ * the largest chunk); 0 for processes with the fused gradient kernel. */
+qed_status qed_eval_grad_workspace_size(const qed_process* p, int64_t N, int64_t* bytes);
 
 /* Mixed-process batches: segments of different processes evaluated by one
  * persistent kernel launch (captured in a HIP graph at plan creation).
@@ -220,73 +230,9 @@ qed_status qed_batch_prebuild(const int* n_list, int count, qed_precision prec, 
 /* Last error message of the calling thread ("" if none). */
 const char* qed_last_error(void);
 
-/* FP64 pipe probe (measurement tool, not part of the evaluation path).
- * After the distributive factoring of the helicity-summed join (Sec. II-B
- * join task, Sec. IV term rewriting), the join of one photon partition is a
- * small dense complex product that could run on the FP64 matrix pipe
- * (v_mfma_f64_16x16x4) beside the vector code that builds the currents.  This
- * call measures that ceiling: blocks workgroups of 256 lanes, launched on
- * stream (hipStream_t, may be NULL):
- *  kind 0, vector pipe: each lane runs 8 chains a <- fma(a, m, c), iters
- *    steps, from a_j = (lane % 64) + j, j = 0..7; out[lane] = sum of the 8
- *    chains (16 iters FLOPs per lane).
- *  kind 1, matrix pipe: each wave runs 4 chains of iters (a multiple of 8)
- *    v_mfma_f64_16x16x4 on C += A.B, A[i][k] = a[i + 16k], B[k][j] =
- *    b[j + 16k] (a, b: 64 doubles each); out[4 * lane + r] = the sum of the 4
- *    accumulators' item r, which holds C[(lane % 64) / 16 + 4r][lane % 16]
- *    (2048 FLOPs per instruction per wave).
- *  kind 2, both: even waves of each workgroup run kind 0 with iters steps
- *    into out, odd waves kind 1 with iters2 steps into out2.
- * All pointers are device buffers sized blocks * 256 (out of kind 0 and 2)
- * or blocks * 1024 doubles (out of kind 1, out2), owned by the caller.
- * Errors: INVALID_ARG for kind outside 0..2, blocks outside 1..2^24,
- * negative counts, matrix-pipe counts not a multiple of 8, or missing
- * buffers. */
-qed_status qed_pipe_probe(int kind, int64_t blocks, int64_t iters, int64_t iters2, double m, double c,
-                          const double* a, const double* b, double* out, double* out2, void* stream);
-/* Compile the probe's code object into the cache (no GPU). */
-qed_status qed_pipe_probe_prebuild(double* compile_ms);
-
 /* Code-object cache directory in use (QEDX_CACHE_DIR or the package default). */
 const char* qed_cache_dir(void);
 
-/* Host-side graph tools (no GPU needed), for inspection and tests.
- * qed_graph_counts: node counts of the generated graph for n, enumerated
- * helicity bits `enum_mask` and join split `split`: reduced = 0 gives the
- * paper's unreduced form (one chain per diagram, S2 joins); reduced = 1 the
- * node-reduced, join-expanded form; reduced = 2 that form after the
- * distributive rewrite (see qed_variant.rewrite).  counts[10] = total, data, compute, U, V,
- * S1, S2, Dot, Sum, HelSum. */
-qed_status qed_graph_counts(int n, int n_in, uint32_t enum_mask, int split, int reduced, int64_t* counts);
-/* Host interpreter of the graph (float64), per point: value of the exit node
- * (sum over enum_mask configurations of |A|^2) with the other bits from hel.
- * reduced as above; mom is host [N][4(n_in+n+2)] (point-major); out host [N]. */
-qed_status qed_graph_interpret(int n, int n_in, uint32_t enum_mask, int split, int reduced, const double* mom,
-                               const uint32_t* hel, int64_t N, double* out);
-/* Canonical structure hash text of the reduced graph reached by (a) the
- * one-pass fixpoint and (b) single reductions in a random order seeded by
- * `seed`; writes at most buflen bytes of each.  Returns the number of single
- * reductions in *steps. */
-qed_status qed_graph_reduction_check(int n, int n_in, uint32_t enum_mask, int split, uint64_t seed, char* canon_a,
-                                     char* canon_b, int64_t buflen, int64_t* steps);
-/* The graph of the reduction experiment (Sec. III-D): the unreduced graph
- * for n outgoing photons, one configuration per point, after the first
- * `steps` single node reductions in the random order seeded by `seed`.
- * Writes counts[10] (as qed_graph_counts) if non-NULL and, for N points
- * (mom host [N][4(n+3)], hel host [N] or NULL), the interpreted |A|^2. */
-qed_status qed_graph_partial(int n, int split, int64_t steps, uint64_t seed, const double* mom, const uint32_t* hel,
-                             int64_t N, double* out, int64_t* counts);
-/* Generated HIP source of the eval kernel for a variant (for inspection and
- * for prebuilding the cache); writes at most buflen bytes, returns the full
- * length in *len. */
-qed_status qed_emit_source(int n, qed_hel_mode mode, qed_precision prec, const qed_variant* variant, char* buf,
-                           int64_t buflen, int64_t* len);
-
-/* C(DAG) and D(DAG) of the graph (App. B graph metrics): compute effort in
- * FLOPs (add/mul 1, fma 2, div/sqrt 1, per point) and data transfer in bytes,
- * with float32 value sizes if fp32 != 0. */
-qed_status qed_graph_metrics(int n, int n_in, uint32_t enum_mask, int split, int reduced, int fp32,
-                             double* c_dag, double* d_dag);
 /* Emit and compile the kernels of one process variant into the code-object
  * cache without touching the GPU (ahead-of-time build).  with_aux = 1 also
  * builds the RAMBO/gradient module.  *compile_ms receives the compile time
@@ -297,17 +243,6 @@ qed_status qed_prebuild(int n, qed_hel_mode mode, qed_precision prec, const qed_
  * arguments); there is no auxiliary module for n_in > 1. */
 qed_status qed_prebuild_crossed(int n_in, int n_out, qed_hel_mode mode, qed_precision prec,
                                 const qed_variant* variant, double* compile_ms);
-
-/* Host references of the gradient pieces (no GPU), for tests:
- * qed_graph_grad_interpret: F = log(sum over all configurations of |A|^2) and
- * dF/dmom by a reverse sweep over the graph in float64.  mom host [N][4(n+3)]
- * point-major; val [N]; gmom [N][4(n+3)] (rows of the incoming particles 0).
- * qed_rambo_vjp_host: final-state momenta mom [N][4(n+1)] from uniforms
- * u [N][4(n+1)], and gu [N][4(n+1)] = (dk/du)^T gk for given gk [N][4(n+1)]. */
-qed_status qed_graph_grad_interpret(int n, int split, int reduced, const double* mom, int64_t N, double* val,
-                                    double* gmom);
-qed_status qed_rambo_vjp_host(int n, const double* u, double sqrt_s, const double* gk, int64_t N, double* mom,
-                              double* gu);
 
 #ifdef __cplusplus
 }

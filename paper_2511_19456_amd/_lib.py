@@ -11,6 +11,7 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqedx.so")
+PROBE_LIB_PATH = os.path.join(_HERE, "libqedx_probe.so")
 
 c_int, c_int64, c_uint32, c_uint64, c_double, c_void_p, c_char_p = (
     ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p,
@@ -59,7 +60,9 @@ SIGNATURES = {
     "qed_process_info": (c_int, [c_void_p, ctypes.POINTER(QedInfo)]),
     "qed_eval": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "qed_rambo": (c_int, [c_void_p, c_void_p, c_double, c_int64, c_void_p, c_void_p]),
-    "qed_eval_grad": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "qed_eval_grad": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
+                              c_int64, c_void_p]),
+    "qed_eval_grad_workspace_size": (c_int, [c_void_p, c_int64, ctypes.POINTER(c_int64)]),
     "qed_batch_plan_create": (c_int, [ctypes.POINTER(QedSegment), c_int, c_int, ctypes.POINTER(c_void_p)]),
     "qed_batch_launch": (c_int, [c_void_p, c_void_p]),
     "qed_batch_plan_destroy": (c_int, [c_void_p]),
@@ -78,9 +81,6 @@ SIGNATURES = {
                              ctypes.POINTER(c_double)]),
     "qed_prebuild_crossed": (c_int, [c_int, c_int, c_int, c_int, ctypes.POINTER(QedVariant),
                                      ctypes.POINTER(c_double)]),
-    "qed_pipe_probe": (c_int, [c_int, c_int64, c_int64, c_int64, c_double, c_double, c_void_p, c_void_p,
-                               c_void_p, c_void_p, c_void_p]),
-    "qed_pipe_probe_prebuild": (c_int, [ctypes.POINTER(c_double)]),
     "qed_graph_grad_interpret": (c_int, [c_int, c_int, c_int, c_void_p, c_int64, c_void_p, c_void_p]),
     "qed_rambo_vjp_host": (c_int, [c_int, c_void_p, c_double, c_void_p, c_int64, c_void_p, c_void_p]),
     "qed_graph_partial": (c_int, [c_int, c_int, c_int64, ctypes.c_uint64, c_void_p, c_void_p, c_int64, c_void_p,
@@ -89,7 +89,15 @@ SIGNATURES = {
                                   ctypes.POINTER(c_double)]),
 }
 
+# the measurement library (include/qedx_probe.h)
+PROBE_SIGNATURES = {
+    "qed_pipe_probe": (c_int, [c_int, c_int64, c_int64, c_int64, c_double, c_double, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_void_p]),
+    "qed_pipe_probe_prebuild": (c_int, [ctypes.POINTER(c_double)]),
+}
+
 _lib = None
+_probe = None
 
 
 class QedError(RuntimeError):
@@ -111,6 +119,23 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def probe_lib():
+    """libqedx_probe.so (FP64 pipe probe); it reports errors through libqedx's
+    qed_last_error."""
+    global _probe
+    if _probe is None:
+        lib()
+        if not os.path.exists(PROBE_LIB_PATH):
+            raise RuntimeError(f"qedx probe library not found at {PROBE_LIB_PATH}; run build()")
+        L = ctypes.CDLL(PROBE_LIB_PATH)
+        for name, (res, args) in PROBE_SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _probe = L
+    return _probe
 
 
 def check(status: int) -> None:

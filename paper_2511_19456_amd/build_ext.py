@@ -29,7 +29,10 @@ LIB = os.path.join(PKG, "libqedx.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["qedx_dag.cpp", "qedx_emit.cpp", "qedx_kernels.cpp", "qedx_runtime.cpp", "qedx_batch.cpp",
-                "qedx_hosttools.cpp", "qedx_probe.cpp"]
+                "qedx_hosttools.cpp"]
+# measurement tool kept out of the evaluation library (include/qedx_probe.h)
+PROBE_SOURCES = ["qedx_probe.cpp"]
+PROBE_LIB = os.path.join(PKG, "libqedx_probe.so")
 DEVICE_HEADERS = ["qedx_device.h", "qedx_rambo.h"]
 
 
@@ -47,16 +50,15 @@ def embed_headers() -> None:
             f.write(out)
 
 
-def build_library(verbose: bool = False) -> None:
-    embed_headers()
-    objs = []
-    cmds = []
-    for s in HOST_SOURCES:
+def _compile_objects(sources, verbose):
+    objs, cmds = [], []
+    for s in sources:
         o = os.path.join(CSRC, "_build", s.replace(".cpp", ".o"))
         os.makedirs(os.path.dirname(o), exist_ok=True)
         objs.append(o)
         cmds.append(["g++", "-std=c++17", "-O2", "-fPIC", "-Wall", "-Wno-unused-function",
-                     "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-c", os.path.join(CSRC, s), "-o", o])
+                     "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-c", os.path.join(CSRC, s), "-o", o]
+                    + HOST_EXTRA_FLAGS)
     with cf.ThreadPoolExecutor(max_workers=len(cmds)) as ex:
         futs = [ex.submit(subprocess.run, c, capture_output=True, text=True) for c in cmds]
         for c, f in zip(cmds, futs):
@@ -65,20 +67,33 @@ def build_library(verbose: bool = False) -> None:
                 raise RuntimeError("compile failed: " + " ".join(c) + "\n" + r.stderr)
             if verbose and r.stderr:
                 print(r.stderr, file=sys.stderr)
-    tmp = LIB + ".tmp"
-    link = ["g++", "-shared", "-o", tmp] + objs + [f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib"]
+    return objs
+
+
+def _link(out, objs, extra):
+    tmp = out + ".tmp"
+    link = ["g++", "-shared", "-o", tmp] + objs + extra + [f"-L{ROCM}/lib", "-lamdhip64",
+                                                          f"-Wl,-rpath,{ROCM}/lib"] + HOST_EXTRA_FLAGS
     r = subprocess.run(link, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: " + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
 
 
-class QedVariant(ctypes.Structure):
-    _fields_ = [("lane_bits", ctypes.c_uint32), ("loop_bits", ctypes.c_uint32), ("block", ctypes.c_int32),
-                ("split", ctypes.c_int32), ("min_waves", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("use_defaults", ctypes.c_int32), ("rewrite", ctypes.c_int32),
-                ("partial", ctypes.c_int32), ("partial_steps", ctypes.c_int32), ("partial_seed", ctypes.c_uint32),
-                ("fixup", ctypes.c_int32), ("fix_kappa", ctypes.c_float)]
+# extra host compile/link flags (e.g. a sanitizer build of the host library);
+# the generated GPU code is compiled by the library itself, never with these
+HOST_EXTRA_FLAGS = os.environ.get("QEDX_HOST_FLAGS", "").split()
+
+
+def build_library(verbose: bool = False) -> None:
+    embed_headers()
+    _link(LIB, _compile_objects(HOST_SOURCES, verbose), [])
+    # the probe library resolves the code-object cache and error reporting
+    # from libqedx.so next to it
+    _link(PROBE_LIB, _compile_objects(PROBE_SOURCES, verbose), [f"-L{PKG}", "-lqedx", "-Wl,-rpath,$ORIGIN"])
+
+
+from paper_2511_19456_amd._lib import QedVariant  # noqa: E402  (ctypes layout of qed_variant)
 
 
 # (n, mode, precision[, variant fields]) built ahead of time: SUM 0 / PER_POINT 1;
@@ -180,7 +195,8 @@ def prebuild_batches(verbose: bool = True) -> None:
 
 
 def prebuild_probe(verbose: bool = True) -> None:
-    lib = ctypes.CDLL(LIB)
+    ctypes.CDLL(LIB, mode=ctypes.RTLD_GLOBAL)
+    lib = ctypes.CDLL(PROBE_LIB)
     lib.qed_pipe_probe_prebuild.argtypes = [ctypes.POINTER(ctypes.c_double)]
     lib.qed_pipe_probe_prebuild.restype = ctypes.c_int
     lib.qed_last_error.restype = ctypes.c_char_p

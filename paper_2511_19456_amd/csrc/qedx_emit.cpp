@@ -945,8 +945,7 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   if (v.min_waves > 0) os << ", " << v.min_waves;
   os << ")\n" << kname
      << "(const double* __restrict__ mom, const unsigned* __restrict__ hel, long long N, double* __restrict__ out"
-     << (v.fixup ? ", double fix_kappa, unsigned* __restrict__ fix_cnt, unsigned* __restrict__ fix_list" : "")
-     << ")\n{\n";
+     << (v.fixup ? ", double fix_kappa" : "") << ")\n{\n";
   const std::string lds_mark = "  //@LDS@\n";
   os << lds_mark;
   os << "  const long long gid = (long long)blockIdx.x * " << v.block << " + threadIdx.x;\n";
@@ -960,19 +959,9 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   e.lane_work(hrt);
   for (int o = 1; o < G; o <<= 1) os << "  acc += __shfl_xor(acc, " << o << ");\n";
   if (v.fixup)
-    // one counter update per wave (ballot, then each flagged lane's rank
-    // among the flagged lanes below it)
-    os << "  if (pt < N && sub == 0u) out[pt] = acc;\n"
-       << "  const bool fx_ = fixflag && pt < N && sub == 0u;\n"
-       << "  const unsigned long long fm_ = __ballot(fx_);\n"
-       << "  if (fm_) {\n"
-       << "    const unsigned ln_ = __lane_id();\n"
-       << "    const unsigned ld_ = (unsigned)__ffsll((unsigned long long)fm_) - 1u;\n"
-       << "    unsigned base_ = 0u;\n"
-       << "    if (ln_ == ld_) base_ = atomicAdd(fix_cnt, (unsigned)__popcll(fm_));\n"
-       << "    base_ = __shfl(base_, (int)ld_);\n"
-       << "    if (fx_) fix_list[base_ + (unsigned)__popcll(fm_ & ((1ull << ln_) - 1ull))] = (unsigned)pt;\n"
-       << "  }\n}\n";
+    // a point the FP32 pass cannot resolve is marked in place with a negative
+    // value (|M|^2 itself is never negative); the FP64 pass below finds it
+    os << "  if (pt < N && sub == 0u) out[pt] = fixflag ? -1.0 : acc;\n}\n";
   else
     os << "  if (pt < N && sub == 0u) out[pt] = acc;\n}\n";
   // per point: every lane of the group does the body once per loop iteration
@@ -996,15 +985,38 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     EmitStats st64;
     std::ostringstream fx;
     fx << emit_body_function(d, v64, kname + "_b64", &st64) << "\n";
-    fx << "extern \"C\" __global__ void __launch_bounds__(64)\n"
-       << kname << "_fix_zero(unsigned* __restrict__ fix_cnt)\n{\n  if (threadIdx.x == 0) fix_cnt[0] = 0u;\n}\n";
+    // Each workgroup of 256 lanes owns kFixRange consecutive points: it scans
+    // their results for the negative marks, compacts the marked offsets in
+    // LDS (one LDS atomic per wave: ballot, then each marked lane's rank
+    // among the marked lanes below it) and recomputes them 256 at a time, so
+    // the FP64 body runs on full waves however sparse the marks are.
     fx << "extern \"C\" __global__ void __launch_bounds__(256)\n"
        << kname << "_fix(const double* __restrict__ mom, const unsigned* __restrict__ hel, long long N, "
-       << "double* __restrict__ out, const unsigned* __restrict__ fix_cnt, const unsigned* __restrict__ fix_list)\n{\n"
-       << "  const long long cnt = (long long)fix_cnt[0];\n"
-       << "  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < cnt; i += (long long)gridDim.x * 256) {\n"
-       << "    const long long pt = (long long)fix_list[i];\n"
-       << "    out[pt] = " << kname << "_b64(mom, N, pt, hel[pt]);\n  }\n}\n";
+       << "double* __restrict__ out)\n{\n"
+       << "  __shared__ unsigned fx_list[" << kFixRange << "];\n"
+       << "  __shared__ unsigned fx_cnt;\n"
+       << "  if (threadIdx.x == 0) fx_cnt = 0u;\n"
+       << "  __syncthreads();\n"
+       << "  const long long base = (long long)blockIdx.x * " << kFixRange << ";\n"
+       << "  const unsigned ln_ = __lane_id();\n"
+       << "  for (unsigned i = threadIdx.x; i < " << kFixRange << "u; i += 256u) {\n"
+       << "    const long long pt = base + (long long)i;\n"
+       << "    const bool f_ = pt < N && out[pt] < 0.0;\n"
+       << "    const unsigned long long fm_ = __ballot(f_);\n"
+       << "    if (fm_) {\n"
+       << "      const unsigned ld_ = (unsigned)__ffsll((unsigned long long)fm_) - 1u;\n"
+       << "      unsigned b_ = 0u;\n"
+       << "      if (ln_ == ld_) b_ = atomicAdd(&fx_cnt, (unsigned)__popcll(fm_));\n"
+       << "      b_ = __shfl(b_, (int)ld_);\n"
+       << "      if (f_) fx_list[b_ + (unsigned)__popcll(fm_ & ((1ull << ln_) - 1ull))] = i;\n"
+       << "    }\n"
+       << "  }\n"
+       << "  __syncthreads();\n"
+       << "  const unsigned cnt = fx_cnt;\n"
+       << "  for (unsigned j = threadIdx.x; j < cnt; j += 256u) {\n"
+       << "    const long long pt = base + (long long)fx_list[j];\n"
+       << "    out[pt] = " << kname << "_b64(mom, N, pt, hel[pt]);\n"
+       << "  }\n}\n";
     src += fx.str();
   }
   e.st.lines = std::count(src.begin(), src.end(), '\n');

@@ -33,6 +33,9 @@ struct Variant {
   int fixup = 0;        // 1: FP32C per-point kernel flags ill-conditioned points for an FP64 pass
 };
 
+// Points scanned by one workgroup of the FP64 fix-up pass.
+constexpr int kFixRange = 4096;
+
 struct EmitStats {
   double flops_per_point = 0;   // algorithmic FLOPs per phase-space point
   int64_t n_V = 0, n_S1 = 0, n_dot = 0, n_prop = 0, n_U = 0;
@@ -51,17 +54,17 @@ Dag graph_for(const Process& proc, const Variant& v, double* t_build, double* t_
 //   extern "C" __global__ void <kname>(const double* mom, const unsigned* hel,
 //                                      long long N, double* out)
 // mom: [4*npart][N] SoA (row = 4*particle + mu), out: [N].
-// With v.fixup (FP32C, per point) the kernel takes three more arguments,
-// (double fix_kappa, unsigned* fix_cnt, unsigned* fix_list), also sums
-// |diagram value|^2 beside the compensated sum, and appends the point index
-// to fix_list (fix_cnt counts) where sqrt of that sum exceeds
-// fix_kappa * |A|: a cancellation the FP32 currents cannot resolve to the
-// stated bound.  The module then also holds
-//   extern "C" __global__ void <kname>_fix_zero(unsigned* fix_cnt)   (one lane clears it)
+// With v.fixup (FP32C, per point) the kernel takes one more argument,
+// (double fix_kappa), also sums |diagram value|^2 beside the compensated sum,
+// and where the square root of that sum exceeds fix_kappa * |A| (a
+// cancellation the FP32 currents cannot resolve to the stated bound) writes
+// -1 to out[pt] instead of the value.  The module then also holds
 //   extern "C" __global__ void <kname>_fix(const double* mom, const unsigned* hel,
-//       long long N, double* out, const unsigned* fix_cnt, const unsigned* fix_list)
-// the latter recomputing the listed points with the FP64 body of the same
-// graph (grid-stride loop over the list, any grid).
+//       long long N, double* out)
+// launched with ceil(N / kFixRange) workgroups of 256 lanes on the same
+// stream: workgroup b scans out[b kFixRange .. (b+1) kFixRange) for negative
+// marks and recomputes those points with the FP64 body of the same graph.
+// No memory beyond the caller's buffers is used.
 std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* st);
 
 // Gradient kernel (SUM mode, FP64, partition-local blocks, no loop bits):

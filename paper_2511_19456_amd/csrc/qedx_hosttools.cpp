@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/qedx.h"
+#include "../../include/qedx_tools.h"
 #include "qedx_dag.hpp"
 
 #define QEDX_HD inline

@@ -28,25 +28,20 @@ struct qed_process {
   hipModule_t mod = nullptr;
   hipFunction_t f_eval = nullptr;
   hipFunction_t f_fix = nullptr;  // FP64 pass of FP32C per-point kernels (null if none)
-  hipFunction_t f_fix_zero = nullptr;
-  unsigned* fix_ws = nullptr;     // [count, list of N point indices], grown on demand
-  size_t fix_bytes = 0;
   hipModule_t mod_aux = nullptr;  // RAMBO and gradient kernels
   hipFunction_t f_rambo = nullptr;
   hipFunction_t f_grad = nullptr;
   int grad_block = 256;
   int grad_lanes = 0;
-  // split gradient (n = 4, 5): kernels and a workspace grown on first use
+  // split gradient (n = 4): kernels; the workspace is the caller's
   int grad_split = 0, amp_lanes = 0, adj_lanes = 0;
   hipFunction_t f_grambo = nullptr, f_gamp = nullptr, f_grvjp = nullptr;
   std::vector<hipFunction_t> f_gadj;
-  double* ws = nullptr;
-  size_t ws_bytes = 0;
   std::string eval_src;
   ~qed_process() {
-    if (ws || fix_ws) (void)hipDeviceSynchronize();
-    if (ws) (void)hipFree(ws);
-    if (fix_ws) (void)hipFree(fix_ws);
+    // launches are asynchronous: wait for any still running before the
+    // code objects they execute are unloaded
+    if (mod || mod_aux) (void)hipDeviceSynchronize();
     if (mod) (void)hipModuleUnload(mod);
     if (mod_aux) (void)hipModuleUnload(mod_aux);
   }
@@ -60,4 +55,14 @@ qed_status get_code_object(const std::string& tag, const std::string& src, std::
 std::string cache_dir();
 // Kernel shape the library uses for (n, mode, prec) when the caller gives none.
 qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, qedx::Variant& v);
+// Gradient pieces shared by qed_eval_grad and its allocation-free variant:
+// argument checks, the fused kernel (n <= 3), and the split kernels over
+// chunks of C points through a workspace of C * grad_ws_per_point bytes.
+int64_t grad_ws_per_point(const qed_process* p);
+qed_status grad_check(const qed_process* p, const double* uniforms, double sqrt_s, const uint32_t* hel, int64_t N,
+                      double* out_logm2, double* out_grad);
+qed_status grad_fused(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N, double* out_logm2,
+                      double* out_grad, void* stream);
+qed_status grad_split_chunks(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N,
+                             double* out_logm2, double* out_grad, double* ws, int64_t C, void* stream);
 }  // namespace qedx_rt

@@ -14,6 +14,7 @@
 #include <mutex>
 #include <string>
 
+#include "../../include/qedx_probe.h"
 #include "qedx_internal.hpp"
 
 using namespace qedx_rt;

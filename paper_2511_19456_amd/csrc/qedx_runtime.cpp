@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "../../include/qedx.h"
+#include "../../include/qedx_tools.h"
 #include "qedx_dag.hpp"
 #include "qedx_emit.hpp"
 #include "qedx_internal.hpp"
@@ -517,7 +518,6 @@ static qed_status process_create(int nin, int n, qed_hel_mode mode, qed_precisio
   if (p->var.fixup) {
     std::string fx = std::string(p->info.kernel_name) + "_fix";
     HIPCHK(hipModuleGetFunction(&p->f_fix, p->mod, fx.c_str()));
-    HIPCHK(hipModuleGetFunction(&p->f_fix_zero, p->mod, (fx + "_zero").c_str()));
   }
   if (nin != 1) {  // RAMBO and the gradient are built for one incoming photon
     p->info.create_ms_load = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -605,33 +605,16 @@ extern "C" qed_status qed_eval(const qed_process* p, const double* momenta, cons
     void* args[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out};
     return launch(p->f_eval, N * (int64_t)p->lanes, p->var.block, stream, args);
   }
-  // FP32C pass listing the ill-conditioned points, then the FP64 pass over
-  // the list (grid-stride, at most 1024 workgroups).  The list lives in a
-  // process-owned workspace of N + 1 words, grown here when N grows.
-  if (N > (int64_t)0xffffffffu) return fail(QED_ERR_INVALID_ARG, "N must be below 2^32 for the FP64 fix-up list");
-  qed_process* q = const_cast<qed_process*>(p);
-  size_t need = sizeof(unsigned) * ((size_t)N + 1);
-  if (q->fix_bytes < need) {
-    if (q->fix_ws) {
-      HIPCHK(hipDeviceSynchronize());
-      HIPCHK(hipFree(q->fix_ws));
-      q->fix_ws = nullptr;
-      q->fix_bytes = 0;
-    }
-    HIPCHK(hipMalloc((void**)&q->fix_ws, need));
-    q->fix_bytes = need;
-  }
-  unsigned* cnt = q->fix_ws;
-  unsigned* list = q->fix_ws + 1;
-  void* zargs[] = {(void*)&cnt};
-  qed_status s = launch(p->f_fix_zero, 64, 64, stream, zargs);
-  if (s) return s;
+  // FP32C pass, which marks the points it cannot resolve with a negative
+  // value in `out`, then the FP64 pass over those marks (one workgroup per
+  // kFixRange points); no memory beyond the caller's buffers
   double kappa = p->info.fix_kappa;
-  void* args[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out, (void*)&kappa, (void*)&cnt, (void*)&list};
-  s = launch(p->f_eval, N * (int64_t)p->lanes, p->var.block, stream, args);
+  void* args[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out, (void*)&kappa};
+  qed_status s = launch(p->f_eval, N * (int64_t)p->lanes, p->var.block, stream, args);
   if (s) return s;
-  void* fargs[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out, (void*)&cnt, (void*)&list};
-  return launch(p->f_fix, std::min<int64_t>(N, 1024 * 256), 256, stream, fargs);
+  void* fargs[] = {(void*)&momenta, (void*)&hel, (void*)&n, (void*)&out};
+  const int64_t fix_groups = (N + kFixRange - 1) / kFixRange;
+  return launch(p->f_fix, fix_groups * 256, 256, stream, fargs);
 }
 
 extern "C" qed_status qed_rambo(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N,
@@ -647,50 +630,44 @@ extern "C" qed_status qed_rambo(const qed_process* p, const double* uniforms, do
   return launch(p->f_rambo, N, 256, stream, args);
 }
 
-extern "C" qed_status qed_eval_grad(const qed_process* p, const double* uniforms, double sqrt_s,
-                                    const uint32_t* hel, int64_t N, double* out_logm2, double* out_grad,
-                                    void* stream) {
-  if (!p) return fail(QED_ERR_INVALID_ARG, "process is NULL");
-  if (p->mode != QED_HEL_SUM || p->prec != QED_FP64 || p->n_in != 1)
-    return fail(QED_ERR_UNSUPPORTED, "gradient is built for SUM-mode FP64 processes with one incoming photon");
-  if (hel) return fail(QED_ERR_INVALID_ARG, "hel must be NULL");
-  if (N < 0) return fail(QED_ERR_INVALID_ARG, "N < 0");
-  if (!(sqrt_s > 1.0) || !std::isfinite(sqrt_s)) return fail(QED_ERR_INVALID_ARG, "sqrt_s must exceed m = 1");
-  if (!p->f_grad && !p->grad_split) return fail(QED_ERR_UNSUPPORTED, "no gradient kernel for this process variant");
-  if (N == 0) return QED_OK;
-  if (!uniforms || !out_logm2 || !out_grad) return fail(QED_ERR_INVALID_ARG, "NULL buffer");
-  if (!p->grad_split) {
-    long long n = (long long)N;
-    void* args[] = {(void*)&uniforms, (void*)&sqrt_s, (void*)&n, (void*)&out_logm2, (void*)&out_grad};
-    return launch(p->f_grad, N * (int64_t)p->grad_lanes, p->grad_block, stream, args);
-  }
-  // Split gradient over chunks of C points.  Workspace per point: momenta and
-  // momentum gradient [4(n+3)] each, amplitudes [2 * 2^(n+3)], 1/|M|^2.
+namespace qedx_rt {
+qed_status grad_fused(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N, double* out_logm2,
+                      double* out_grad, void* stream);
+}
+
+// Split gradient: bytes of workspace per point (momenta and momentum
+// gradient [4 npart] each, amplitudes [2 H], 1/|M|^2) and the largest chunk
+// of points one pass takes (a power of two, at most 2^20 and 320 MB).
+static int64_t grad_ws_per_point(const qed_process* p) {
   const int npart = p->n + p->n_in + 2;
   const int64_t H = (int64_t)1 << npart;
-  const int64_t per_pt = 8 * (2 * 4 * (int64_t)npart + 2 * H + 1);
+  return 8 * (2 * 4 * (int64_t)npart + 2 * H + 1);
+}
+
+static int64_t grad_max_chunk(const qed_process* p) {
   int64_t C = (int64_t)1 << 20;
-  while (C > 256 && C * per_pt > ((int64_t)320 << 20)) C >>= 1;
-  if (C > N) C = N;
-  const size_t need = (size_t)(C * per_pt);
-  qed_process* pm = const_cast<qed_process*>(p);  // the workspace is the only mutable state
-  if (pm->ws_bytes < need) {
-    if (pm->ws) {
-      HIPCHK(hipStreamSynchronize((hipStream_t)stream));
-      (void)hipFree(pm->ws);
-      pm->ws = nullptr;
-      pm->ws_bytes = 0;
-    }
-    if (hipMalloc((void**)&pm->ws, need) != hipSuccess) {
-      pm->ws = nullptr;
-      return fail(QED_ERR_OOM, "gradient workspace allocation failed");
-    }
-    pm->ws_bytes = need;
-  }
+  while (C > 256 && C * grad_ws_per_point(p) > ((int64_t)320 << 20)) C >>= 1;
+  return C;
+}
+
+extern "C" qed_status qed_eval_grad_workspace_size(const qed_process* p, int64_t N, int64_t* bytes) {
+  if (!p || !bytes) return fail(QED_ERR_INVALID_ARG, "NULL argument");
+  if (N < 0) return fail(QED_ERR_INVALID_ARG, "N < 0");
+  *bytes = p->grad_split ? grad_ws_per_point(p) * std::min<int64_t>(N, grad_max_chunk(p)) : 0;
+  return QED_OK;
+}
+
+// The split gradient over chunks of C points through a workspace of
+// C * grad_ws_per_point bytes (any device memory of that size: the caller's
+// workspace, or the allocation-free entry point's static buffer).
+static qed_status grad_split_chunks(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N,
+                                    double* out_logm2, double* out_grad, double* ws, int64_t C, void* stream) {
+  const int npart = p->n + p->n_in + 2;
+  const int64_t H = (int64_t)1 << npart;
   for (int64_t off = 0; off < N; off += C) {
     long long cnt = (long long)std::min<int64_t>(C, N - off);
     long long ldu = (long long)N;
-    double* mom = pm->ws;
+    double* mom = ws;
     double* gm = mom + 4 * (int64_t)npart * cnt;
     double* amp = gm + 4 * (int64_t)npart * cnt;
     double* im2 = amp + 2 * H * cnt;
@@ -710,6 +687,36 @@ extern "C" qed_status qed_eval_grad(const qed_process* p, const double* uniforms
     if ((st = launch(p->f_grvjp, cnt, 256, stream, a4))) return st;
   }
   return QED_OK;
+}
+
+static qed_status grad_check(const qed_process* p, const double* uniforms, double sqrt_s, const uint32_t* hel,
+                             int64_t N, double* out_logm2, double* out_grad) {
+  if (!p) return fail(QED_ERR_INVALID_ARG, "process is NULL");
+  if (p->mode != QED_HEL_SUM || p->prec != QED_FP64 || p->n_in != 1)
+    return fail(QED_ERR_UNSUPPORTED, "gradient is built for SUM-mode FP64 processes with one incoming photon");
+  if (!p->f_grad && !p->grad_split) return fail(QED_ERR_UNSUPPORTED, "no gradient kernel for this process (n > 4)");
+  if (hel) return fail(QED_ERR_INVALID_ARG, "hel must be NULL");
+  if (N < 0) return fail(QED_ERR_INVALID_ARG, "N < 0");
+  if (!(sqrt_s > 1.0) || !std::isfinite(sqrt_s)) return fail(QED_ERR_INVALID_ARG, "sqrt_s must exceed m = 1");
+  if (N > 0 && (!uniforms || !out_logm2 || !out_grad)) return fail(QED_ERR_INVALID_ARG, "NULL buffer");
+  if (N > (int64_t)1 << 40) return fail(QED_ERR_INVALID_ARG, "N too large");
+  return QED_OK;
+}
+
+extern "C" qed_status qed_eval_grad(const qed_process* p, const double* uniforms, double sqrt_s,
+                                    const uint32_t* hel, int64_t N, double* out_logm2, double* out_grad,
+                                    void* workspace, int64_t workspace_bytes, void* stream) {
+  qed_status s = grad_check(p, uniforms, sqrt_s, hel, N, out_logm2, out_grad);
+  if (s || N == 0) return s;
+  if (!p->grad_split) return qedx_rt::grad_fused(p, uniforms, sqrt_s, N, out_logm2, out_grad, stream);
+  const int64_t per_pt = grad_ws_per_point(p);
+  const int64_t need_min = per_pt * std::min<int64_t>(N, 64);
+  if (!workspace || workspace_bytes < need_min)
+    return fail(QED_ERR_INVALID_ARG, "workspace of at least " + std::to_string(need_min) +
+                                         " bytes required (qed_eval_grad_workspace_size gives the full size)");
+  if ((uintptr_t)workspace % 8) return fail(QED_ERR_INVALID_ARG, "workspace must be 8-byte aligned");
+  const int64_t C = std::min(N, std::min(workspace_bytes / per_pt, grad_max_chunk(p)));
+  return grad_split_chunks(p, uniforms, sqrt_s, N, out_logm2, out_grad, (double*)workspace, C, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -820,6 +827,21 @@ qed_status get_code_object(const std::string& tag, const std::string& src, std::
   return ::get_code_object(tag, src, co, meta, hit, ms);
 }
 std::string cache_dir() { return cache_dir_str(); }
+int64_t grad_ws_per_point(const qed_process* p) { return ::grad_ws_per_point(p); }
+qed_status grad_check(const qed_process* p, const double* uniforms, double sqrt_s, const uint32_t* hel, int64_t N,
+                      double* out_logm2, double* out_grad) {
+  return ::grad_check(p, uniforms, sqrt_s, hel, N, out_logm2, out_grad);
+}
+qed_status grad_fused(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N, double* out_logm2,
+                      double* out_grad, void* stream) {
+  long long n = (long long)N;
+  void* args[] = {(void*)&uniforms, (void*)&sqrt_s, (void*)&n, (void*)&out_logm2, (void*)&out_grad};
+  return launch(p->f_grad, N * (int64_t)p->grad_lanes, p->grad_block, stream, args);
+}
+qed_status grad_split_chunks(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N,
+                             double* out_logm2, double* out_grad, double* ws, int64_t C, void* stream) {
+  return ::grad_split_chunks(p, uniforms, sqrt_s, N, out_logm2, out_grad, ws, C, stream);
+}
 qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, qedx::Variant& v) {
   return make_variant(n, 1, mode, prec, nullptr, v);
 }

@@ -135,9 +135,19 @@ class QedProcess:
         check(lib().qed_rambo(self._h, _ptr(uniforms), float(sqrt_s), N, _ptr(out), _stream()))
         return out
 
-    def eval_grad(self, uniforms: torch.Tensor, sqrt_s: float, out: Optional[tuple] = None):
+    def grad_workspace_bytes(self, N: int) -> int:
+        """Device workspace qed_eval_grad uses for N points in one chunk."""
+        b = ctypes.c_int64()
+        check(lib().qed_eval_grad_workspace_size(self._h, int(N), ctypes.byref(b)))
+        return b.value
+
+    def eval_grad(self, uniforms: torch.Tensor, sqrt_s: float, out: Optional[tuple] = None,
+                  workspace: Optional[torch.Tensor] = None):
         """(log|M|^2 [N], d log|M|^2 / d uniforms [4(n+1), N]) through RAMBO.
-        `out` = (val, grad) preallocated device tensors, or None."""
+        `out` = (val, grad) preallocated device tensors, or None.  `workspace`
+        is a uint8 device tensor for the split gradient (n = 4); by default
+        one chunk's worth is taken from torch's allocator on the current
+        stream."""
         _dev_tensor(uniforms, torch.float64, 4 * (self.n + 1), "uniforms")
         N = uniforms.shape[1]
         if out is None:
@@ -149,29 +159,32 @@ class QedProcess:
             if val.shape != (N,) or val.dtype != torch.float64 or not val.is_cuda or not val.is_contiguous() \
                     or grad.shape[1] != N:
                 raise ValueError("out must be (float64 [N], float64 [4(n+1), N]) contiguous device tensors")
+        if workspace is None:
+            nb = self.grad_workspace_bytes(N)
+            workspace = torch.empty(nb, dtype=torch.uint8, device=uniforms.device) if nb else None
+        elif workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 device tensor")
+        nbytes = 0 if workspace is None else workspace.numel()
         check(lib().qed_eval_grad(self._h, _ptr(uniforms), float(sqrt_s), None, N, _ptr(val), _ptr(grad),
-                                  _stream()))
+                                  _ptr(workspace), nbytes, _stream()))
         return val, grad
 
 
 class QedLogM2(torch.autograd.Function):
     """log|M|^2 (helicity sum) of RAMBO points as a differentiable function of
-    the uniforms.  Forward and backward both call the library; the backward
-    reruns the fused forward+adjoint kernel, so nothing but the inputs is saved."""
+    the uniforms.  The forward calls qed_eval_grad, which returns log|M|^2 and
+    its gradient from one pass of the library's kernels; the gradient is kept
+    for the backward, which only scales it by grad_output."""
 
     @staticmethod
     def forward(ctx, uniforms: torch.Tensor, proc: QedProcess, sqrt_s: float):
-        mom = proc.rambo(uniforms.contiguous(), sqrt_s)
-        val = torch.log(proc.eval(mom))
-        ctx.save_for_backward(uniforms)
-        ctx.proc = proc
-        ctx.sqrt_s = sqrt_s
+        val, g = proc.eval_grad(uniforms.contiguous(), sqrt_s)
+        ctx.save_for_backward(g)
         return val
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
-        (u,) = ctx.saved_tensors
-        _, g = ctx.proc.eval_grad(u.contiguous(), ctx.sqrt_s)
+        (g,) = ctx.saved_tensors
         return g * grad_out[None, :], None, None
 
 

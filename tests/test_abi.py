@@ -1,5 +1,5 @@
-"""The C ABI: the library loads without a GPU and exports every function
-declared in include/qedx.h; the generated kernel source is self-contained."""
+"""The C ABI: the libraries load without a GPU and export every function
+declared in include/*.h; the generated kernel source is self-contained."""
 import ctypes
 import os
 import re
@@ -12,24 +12,43 @@ from paper_2511_19456_amd import qedx as Q
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    names = []
-    for f in os.listdir(os.path.join(ROOT, "include")):
-        if f.endswith(".h"):
-            txt = open(os.path.join(ROOT, "include", f)).read()
-            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(qed_\w+)\s*\(", txt, flags=re.M)
-    return sorted(set(names))
+def _declared(header):
+    txt = open(os.path.join(ROOT, "include", header)).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(qed_\w+)\s*\(", txt, flags=re.M)))
+
+
+# header -> (library that exports it, the binding's signature table)
+HEADERS = {"qedx.h": (_lib.LIB_PATH, _lib.SIGNATURES), "qedx_tools.h": (_lib.LIB_PATH, _lib.SIGNATURES),
+           "qedx_probe.h": (_lib.PROBE_LIB_PATH, _lib.PROBE_SIGNATURES)}
 
 
 def test_every_declared_symbol_is_exported():
-    L = ctypes.CDLL(_lib.LIB_PATH)
-    names = _declared()
-    assert len(names) >= 15
-    for n in names:
-        assert hasattr(L, n), n
-    # and the binding declares every one of them
-    assert set(names) <= set(_lib.SIGNATURES)
+    assert sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")) == sorted(HEADERS)
+    _lib.lib()  # the probe library resolves its runtime from libqedx.so
+    total = 0
+    for header, (path, sigs) in HEADERS.items():
+        L = ctypes.CDLL(path)
+        names = _declared(header)
+        total += len(names)
+        for n in names:
+            assert hasattr(L, n), (header, n)
+        # and the binding declares every one of them
+        assert set(names) <= set(sigs), (header, set(names) - set(sigs))
+    assert total >= 20
+
+
+def test_product_header_holds_no_tools():
+    """The evaluation ABI (qedx.h) declares the entry points of the hot path
+    and their build/inspection calls only; host tools and the probe live in
+    their own headers."""
+    prod = set(_declared("qedx.h"))
+    assert not prod & set(_declared("qedx_tools.h"))
+    assert not any(n.startswith("qed_pipe_probe") for n in prod)
+    assert not any(n.startswith("qed_graph_") for n in prod)
+    for n in ("qed_process_create", "qed_eval", "qed_rambo", "qed_eval_grad", "qed_batch_plan_create",
+              "qed_batch_launch", "qed_process_info"):
+        assert n in prod
 
 
 def test_emitted_source_is_self_contained():
@@ -59,7 +78,9 @@ def test_null_process_and_negative_sizes():
     L = _lib.lib()
     assert L.qed_eval(None, None, None, 0, None, None) == _lib.QED_ERR_INVALID_ARG
     assert L.qed_rambo(None, None, 10.0, 0, None, None) == _lib.QED_ERR_INVALID_ARG
-    assert L.qed_eval_grad(None, None, 10.0, None, 0, None, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert L.qed_eval_grad(None, None, 10.0, None, 0, None, None, None, 0, None) == _lib.QED_ERR_INVALID_ARG
+    b = ctypes.c_int64()
+    assert L.qed_eval_grad_workspace_size(None, 10, ctypes.byref(b)) == _lib.QED_ERR_INVALID_ARG
 
 
 def test_compile_failure_is_reported(tmp_path, monkeypatch):
@@ -112,10 +133,11 @@ def test_status_codes_for_crossed_processes_and_the_pipe_probe():
     v = Q.make_variant(fix_kappa=0.5)
     assert L.qed_prebuild(3, 1, 1, ctypes.byref(v), 0, ctypes.byref(ms)) == _lib.QED_ERR_INVALID_ARG
     # pipe probe: kind, sizes, iteration counts and buffers are checked first
-    assert L.qed_pipe_probe(3, 1, 8, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
-    assert L.qed_pipe_probe(0, 0, 8, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
-    assert L.qed_pipe_probe(1, 1, 7, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
-    assert L.qed_pipe_probe(0, 1, 8, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
+    P = _lib.probe_lib()
+    assert P.qed_pipe_probe(3, 1, 8, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert P.qed_pipe_probe(0, 0, 8, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert P.qed_pipe_probe(1, 1, 7, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
+    assert P.qed_pipe_probe(0, 1, 8, 0, 1.0, 0.0, None, None, None, None, None) == _lib.QED_ERR_INVALID_ARG
 
 
 def test_fp32c_per_point_source_has_the_fp64_pass():

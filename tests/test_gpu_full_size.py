@@ -13,6 +13,7 @@ import torch
 
 from oracle import qed_oracle as O
 from paper_2511_19456_amd import inputs
+from parity import check_fp64, per_point_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -81,9 +82,11 @@ def test_full_size_n5_per_point_2p20(prec):
     assert bool(torch.isfinite(out).all()) and bool((out >= 0).all())
     idx = _samples(N, 24)
     ref_mom = O.momenta_soa_from_uniforms(u[:, idx], rs, n)
-    ref = O.m2(ref_mom, n, "per_point", h[idx]).numpy()
-    tol = 1e-10 if prec == "fp64" else 1e-4
-    assert np.abs(out[idx].cpu().numpy() / ref - 1).max() < tol
+    ref, kap = per_point_ref(ref_mom, n, h[idx])
+    if prec == "fp64":
+        check_fp64(out[idx].cpu().numpy(), ref, kap, "n=5 per point")
+    else:
+        assert np.abs(out[idx].cpu().numpy() / ref - 1).max() < 1e-4
     if prec == "fp32c":
         o64 = _proc(n, "per_point", "fp64").eval(mom, hd)
         assert (((out - o64).abs() / o64.abs()).max().item()) < 1e-4
@@ -110,30 +113,29 @@ def test_full_size_mixed_batch(prec):
         s[3].fill_(float("nan"))
     plan.launch()
     torch.cuda.synchronize()
-    tol = 1e-10 if prec == "fp64" else 1e-4
     for (p, mom, hd, out), (n, Np, rs, u, h) in zip(segs, keep):
         assert bool(torch.isfinite(out).all()) and bool((out >= 0).all()), n
         idx = _samples(Np, 6 if n == 6 else 12)
         ref_mom = O.momenta_soa_from_uniforms(u[:, idx], rs, n)
-        ref = O.m2(ref_mom, n, "per_point", h[idx]).numpy()
-        assert np.abs(out[idx].cpu().numpy() / ref - 1).max() < tol, n
-        if prec == "fp32c":
-            # every point against the FP64 kernel (itself pinned above), the
-            # denominator floored at 1e-3 of the segment's median: within
-            # 1e-4 but for at most 2 points per segment (configurations whose
-            # diagrams are small without cancelling between them, which the
-            # FP64 pass does not list), and never beyond 3e-4.  Without the
-            # batch's FP64 pass the n = 5 and 6 segments exceed 1e-3.
+        ref, kap = per_point_ref(ref_mom, n, h[idx])
+        if prec == "fp64":
+            check_fp64(out[idx].cpu().numpy(), ref, kap, f"batch segment n={n}")
+        else:
+            assert np.abs(out[idx].cpu().numpy() / ref - 1).max() < 1e-4, n
+            # every point against the FP64 kernel (itself pinned above):
+            # plain relative error below 1e-4, no floor, no allowance
             o64 = _proc(n, "per_point", "fp64").eval(mom, hd)
-            den = torch.clamp(o64.abs(), min=1e-3 * o64.abs().median().item())
-            err = (out - o64).abs() / den
-            assert int((err > 1e-4).sum().item()) <= 2, n
-            assert err.max().item() < 3e-4, n
+            err = ((out - o64).abs() / o64.abs())
+            assert err.max().item() < 1e-4, (n, err.max().item(), int((err > 1e-4).sum().item()))
 
 
 def test_full_size_gradient_n4_2p18():
-    """2^18 points at sqrt(s) = 15: log|M|^2 and its gradient through RAMBO,
-    sampled against the oracle's reverse-mode gradient."""
+    """2^18 points at sqrt(s) = 15, as the bench runs them: log|M|^2 and its
+    gradient through RAMBO.  The first 1,024 points against the oracle's
+    reverse-mode gradient stored in tests/golden/ (written from oracle/ only),
+    1e-10 normwise; samples over the rest of the batch against the oracle
+    computed here."""
+    import os
     wl = inputs.WORKLOADS["grad_n4_sum_rs15_2p18"]
     n, N, rs = wl["n"], wl["N"], wl["sqrt_s"]
     print(f"full size gradient n=4 N={N}", flush=True)
@@ -141,8 +143,18 @@ def test_full_size_gradient_n4_2p18():
     p = _proc(n, "sum")
     val, g = p.eval_grad(torch.as_tensor(u, device=DEV), rs)
     assert bool(torch.isfinite(val).all()) and bool(torch.isfinite(g).all())
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "grad_n4_rs15_seed5_first1024.npz"))
+    v_o, g_o = gold["logm2"], gold["grad"]
+    K = v_o.shape[0]
+    assert K == 1024 and g_o.shape == (4 * (n + 1), K)
+    vv, gg = val[:K].cpu().numpy(), g[:, :K].cpu().numpy()
+    assert np.abs(vv - v_o).max() < 1e-10 * max(1.0, np.abs(v_o).max())
+    err = np.linalg.norm(gg - g_o, axis=0) / np.linalg.norm(g_o, axis=0)
+    print(f"gradient vs stored oracle on {K} points: max {err.max():.2e} median {np.median(err):.2e}")
+    assert err.max() < 1e-10
     idx = _samples(N, 8)
-    v_o, g_o = O.logm2_and_grad(u[:, idx], rs, n)
-    assert np.abs(val[idx].cpu().numpy() - v_o.numpy()).max() < 1e-10 * max(1.0, np.abs(v_o.numpy()).max())
-    gg, go = g[:, idx].cpu().numpy(), g_o.numpy()
-    assert (np.linalg.norm(gg - go, axis=0) / np.linalg.norm(go, axis=0)).max() < 1e-10
+    idx = idx[idx >= K]
+    v_s, g_s = O.logm2_and_grad(u[:, idx], rs, n)
+    assert np.abs(val[idx].cpu().numpy() - v_s.numpy()).max() < 1e-10 * max(1.0, np.abs(v_s.numpy()).max())
+    gs = g[:, idx].cpu().numpy()
+    assert (np.linalg.norm(gs - g_s.numpy(), axis=0) / np.linalg.norm(g_s.numpy(), axis=0)).max() < 1e-10

@@ -2,7 +2,10 @@
 
 Inputs are the seeded synthetic workloads (inputs.py); the oracle computes its
 own momenta from the same uniforms with its own RAMBO.  Tolerances: 1e-10
-relative for FP64 (stated target), 1e-4 for the compensated FP32 path.
+relative for FP64 (stated target), widened per configuration only by the
+rounding its own cancellation costs (tests/parity.py: 2 C eps kappa with
+kappa = sum |term| / |A| from the oracle); plain 1e-4 relative on every point
+for the compensated FP32 path.
 """
 import math
 
@@ -12,6 +15,7 @@ import torch
 
 from oracle import qed_oracle as O
 from paper_2511_19456_amd import inputs
+from parity import check_fp64, per_point_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -67,12 +71,8 @@ def test_per_point_fp64(n, sqrt_s):
     p = _proc(n, "per_point")
     got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV),
                  torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
-    ref = O.m2(ref_mom, n, "per_point", hel).numpy()
-    # per-configuration values can be tiny where diagrams cancel; compare
-    # relative to the helicity-averaged scale of the point as well
-    scale = O.m2(ref_mom, n, "sum").numpy() / (1 << (n + 3))
-    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
-    assert err.max() < 1e-10
+    ref, kap = per_point_ref(ref_mom, n, hel)
+    check_fp64(got, ref, kap, f"per point n={n}")
 
 
 def test_per_point_sums_to_sum_mode():
@@ -113,9 +113,11 @@ def test_schedule_variants_n3(mode, lanes, order, loop):
     p = _proc(n, mode, "fp64", make_variant(lane_bits=lanes, loop_bits=loop, order=order))
     h = torch.as_tensor(hel.astype(np.int32), device=DEV) if mode == "per_point" else None
     got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV), h).cpu().numpy()
-    ref = O.m2(ref_mom, n, mode, hel).numpy()
-    scale = O.m2(ref_mom, n, "sum").numpy() / (1 << (n + 3))
-    assert (np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * scale)).max() < 1e-10
+    if mode == "sum":
+        assert _rel(got, O.m2(ref_mom, n, "sum").numpy()).max() < 1e-10
+    else:
+        ref, kap = per_point_ref(ref_mom, n, hel)
+        check_fp64(got, ref, kap, f"schedule {order}")
 
 
 def test_per_point_n4_and_sum_n4():
@@ -125,9 +127,9 @@ def test_per_point_n4_and_sum_n4():
     md = torch.as_tensor(ref_mom.numpy(), device=DEV)
     pp = _proc(n, "per_point")
     got = pp.eval(md, torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
-    ref = O.m2(ref_mom, n, "per_point", hel).numpy()
+    ref, kap = per_point_ref(ref_mom, n, hel)
+    check_fp64(got, ref, kap, "per point n=4")
     tot = O.m2(ref_mom, n, "sum").numpy()
-    assert (np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * tot / 128)).max() < 1e-10
     ps = _proc(n, "sum")
     assert _rel(ps.eval(md).cpu().numpy(), tot).max() < 1e-10
 
@@ -144,11 +146,7 @@ def test_fp32c_error_bound(n, mode, sqrt_s):
     h = torch.as_tensor(hel.astype(np.int32), device=DEV) if mode == "per_point" else None
     got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV), h).cpu().numpy()
     ref = O.m2(ref_mom, n, mode, hel).numpy()
-    if mode == "sum":
-        err = _rel(got, ref)
-    else:
-        scale = O.m2(ref_mom, n, "sum").numpy() / (1 << (n + 3))
-        err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
+    err = _rel(got, ref)   # plain relative error on every point, no floor
     print(f"fp32c n={n} {mode}: max {err.max():.2e} p99 {np.quantile(err, 0.99):.2e} median {np.median(err):.2e}")
     assert err.max() < 1e-4
     assert np.median(err) < 1e-5
@@ -217,10 +215,6 @@ def test_gradient_vs_central_differences_and_autograd():
 # ---------------------------------------------------------------------------
 # mixed-process batch: one persistent launch over segments n = 1..6
 # ---------------------------------------------------------------------------
-def _per_point_err(got, ref, scale):
-    return np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
-
-
 @pytest.mark.parametrize("n,sqrt_s,N", [(6, 25.0, 40)])
 def test_per_point_n6_fp64(n, sqrt_s, N):
     u, hel = inputs.rambo_inputs(23, n, N, with_helicities=True)
@@ -228,11 +222,8 @@ def test_per_point_n6_fp64(n, sqrt_s, N):
     p = _proc(n, "per_point")
     got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV),
                  torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
-    ref = O.m2(ref_mom, n, "per_point", hel).numpy()
-    # scale: mean |A_h|^2 over the configurations, from 8 random configurations per point
-    hs = np.stack([inputs.helicities(inputs.rng_for(99 + k), n, N) for k in range(8)])
-    scale = np.mean([O.m2(ref_mom, n, "per_point", h).numpy() for h in hs], axis=0)
-    assert _per_point_err(got, ref, scale).max() < 1e-10
+    ref, kap = per_point_ref(ref_mom, n, hel)
+    check_fp64(got, ref, kap, "per point n=6")
 
 
 @pytest.mark.parametrize("prec,tile,rewrite", [("fp64", 128, 0), ("fp64", 0, 0), ("fp32c", 0, 0), ("fp64", 256, 1)])
@@ -251,9 +242,8 @@ def test_mixed_batch_matches_per_process_and_oracle(prec, tile, rewrite):
         # reference: the plain per-process FP64 kernel on the same inputs
         refs.append(_proc(n, "per_point", "fp64").eval(mom, h) if N else out.clone())
         checks.append((n, u, hel, rs))
-    # FP64: the same generated body as the per-process kernel, so agreement to
-    # rounding; FP32C: the stated bound of the compensated FP32 path
-    tol = 1e-10 if prec == "fp64" else 1e-4
+    # FP64: every point against the oracle (below); FP32C: every point within
+    # the stated bound of the compensated FP32 path against the FP64 kernel
     plan = BatchPlan(segs, tile_points=tile)
     info = plan.info()
     print(f"batch {prec} tile={tile}: {info}")
@@ -267,21 +257,22 @@ def test_mixed_batch_matches_per_process_and_oracle(prec, tile, rewrite):
             if out.numel() == 0:
                 continue
             assert torch.isfinite(out).all(), (n, rep)
-            # relative to the point's value, floored at 1e-3 of the segment's median
-            floor = 1e-3 * ref.abs().median()
-            assert ((out - ref).abs() / torch.maximum(ref.abs(), floor)).max().item() < tol, (n, rep)
-    # sampled points against the oracle (FP64 batches)
+            if prec == "fp64":
+                # the same generated body as the per-process kernel
+                assert torch.equal(out, ref) or ((out - ref).abs() / ref.abs()).max().item() < 1e-12, (n, rep)
+            else:
+                assert ((out - ref).abs() / ref.abs()).max().item() < 1e-4, (n, rep)
+    # every point of every FP64 segment against the oracle
     if prec == "fp64":
         for (p, mom, h, out), (n, u, hel, rs) in zip(segs, checks):
             N = out.numel()
             if N == 0:
                 continue
-            idx = np.unique(np.linspace(0, N - 1, 24 if n < 6 else 6).astype(int))
-            ref_mom = O.momenta_soa_from_uniforms(u[:, idx], rs, n)
-            ref = O.m2(ref_mom, n, "per_point", hel[idx]).numpy()
-            tot = O.m2(ref_mom, n, "sum").numpy() if n < 5 else np.abs(ref)
-            scale = tot / (1 << (n + 3)) if n < 5 else np.abs(ref)
-            assert _per_point_err(out.cpu().numpy()[idx], ref, scale).max() < 1e-10, n
+            ref_mom = O.momenta_soa_from_uniforms(u, rs, n)
+            # the batch ran on the device RAMBO's momenta; the oracle's agree to 1e-12 sqrt(s)
+            assert (mom.cpu() - ref_mom).abs().max().item() < 1e-12 * rs
+            ref, kap = per_point_ref(mom.cpu().numpy(), n, hel)
+            check_fp64(out.cpu().numpy(), ref, kap, f"batch segment n={n}")
 
 
 # ---------------------------------------------------------------------------
@@ -301,12 +292,10 @@ def test_distributive_rewrite_fp64(n, mode, sqrt_s, lanes, N):
     got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV), h).cpu().numpy()
     ref = O.m2(ref_mom, n, mode, hel).numpy()
     if mode == "sum":
-        err = _rel(got, ref)
+        assert _rel(got, ref).max() < 1e-10
     else:
-        # per-configuration values: relative to the point's value, floored at
-        # 1e-3 of the segment's median (values can vanish where diagrams cancel)
-        err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * np.median(np.abs(ref)))
-    assert err.max() < 1e-10
+        ref, kap = per_point_ref(ref_mom, n, hel)
+        check_fp64(got, ref, kap, f"distributive n={n}")
 
 
 @pytest.mark.parametrize("n,mode,sqrt_s", [(3, "sum", 10.0), (5, "per_point", 20.0)])
@@ -319,11 +308,7 @@ def test_distributive_rewrite_fp32c(n, mode, sqrt_s):
     h = torch.as_tensor(hel.astype(np.int32), device=DEV) if mode == "per_point" else None
     got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV), h).cpu().numpy()
     ref = O.m2(ref_mom, n, mode, hel).numpy()
-    if mode == "sum":
-        err = _rel(got, ref)
-    else:
-        scale = O.m2(ref_mom, n, "sum").numpy() / (1 << (n + 3))
-        err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * scale)
+    err = _rel(got, ref)
     print(f"fp32c rewrite n={n} {mode}: max {err.max():.2e} p99 {np.quantile(err, 0.99):.2e} "
           f"median {np.median(err):.2e}")
     assert err.max() < 1e-4
@@ -343,9 +328,8 @@ def test_partially_reduced_kernels(steps):
     assert p.info()["kernel_tag"].endswith(f"_k{steps}s1")
     got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV),
                  torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
-    ref = O.m2(ref_mom, n, "per_point", hel).numpy()
-    tot = O.m2(ref_mom, n, "sum").numpy()
-    assert (np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * tot / 128)).max() < 1e-10
+    ref, kap = per_point_ref(ref_mom, n, hel)
+    check_fp64(got, ref, kap, f"partial {steps}")
 
 
 # Table I orientation e- gamma^n_in -> e- gamma^n_out (crossed processes).
@@ -380,9 +364,11 @@ def test_crossed_processes(n_in, n_out, mode, prec, rewrite, N):
         assert _rel(got, tot).max() < tol
     else:
         got = p.eval(md, torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
-        ref = O.m2(mom, n_out, "per_point", hel, n_in=n_in).numpy()
-        err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * tot / (1 << npart))
-        assert err.max() < tol
+        ref, kap = per_point_ref(mom, n_out, hel, n_in=n_in)
+        if prec == "fp64":
+            check_fp64(got, ref, kap, f"crossed {n_in}->{n_out}")
+        else:
+            assert _rel(got, ref).max() < tol
     with pytest.raises(QedError):
         p.rambo(torch.zeros(4 * (n_out + 1), 4, dtype=torch.float64, device=DEV), 10.0)
 
@@ -391,7 +377,7 @@ def test_fp64_pipe_probe_closed_forms():
     """The pipe probe's kernels do the work they are timed for: the vector
     chains match the closed form of a <- a m + c, the matrix chains 4 iters A.B
     with the stated operand and result lane layouts (dyadic inputs: exact)."""
-    from paper_2511_19456_amd._lib import check, lib
+    from paper_2511_19456_amd._lib import check, probe_lib
     blocks, it_v, it_m = 3, 1000, 64
     mm, cc = 0.999, 0.001
     av = (torch.arange(64, dtype=torch.float64) + 1) / 64.0
@@ -411,16 +397,16 @@ def test_fp64_pipe_probe_closed_forms():
     for r in range(4):
         # item r of lane l holds row l/16 + 4r, column l%16
         expect_m[4 * lanes + r] = C[(lanes % 64) // 16 + 4 * r, lanes % 16]
-    check(lib().qed_pipe_probe(0, blocks, it_v, 0, mm, cc, None, None, ov.data_ptr(), None, st))
+    check(probe_lib().qed_pipe_probe(0, blocks, it_v, 0, mm, cc, None, None, ov.data_ptr(), None, st))
     torch.cuda.synchronize()
     assert np.max(np.abs(ov.cpu().numpy() / chains - 1)) < 1e-12
-    check(lib().qed_pipe_probe(1, blocks, it_m, 0, mm, cc, a_d.data_ptr(), b_d.data_ptr(), om.data_ptr(),
+    check(probe_lib().qed_pipe_probe(1, blocks, it_m, 0, mm, cc, a_d.data_ptr(), b_d.data_ptr(), om.data_ptr(),
                                None, st))
     torch.cuda.synchronize()
     assert np.array_equal(om.cpu().numpy(), expect_m)
     ov.fill_(-1.0)
     om.fill_(-1.0)
-    check(lib().qed_pipe_probe(2, blocks, it_v, it_m, mm, cc, a_d.data_ptr(), b_d.data_ptr(), ov.data_ptr(),
+    check(probe_lib().qed_pipe_probe(2, blocks, it_v, it_m, mm, cc, a_d.data_ptr(), b_d.data_ptr(), ov.data_ptr(),
                                om.data_ptr(), st))
     torch.cuda.synchronize()
     even = ((lanes // 64) % 2) == 0
@@ -431,12 +417,11 @@ def test_fp64_pipe_probe_closed_forms():
 
 @pytest.mark.parametrize("n,sqrt_s", [(3, 10.0), (5, 20.0)])
 def test_fp32c_fp64_fixup(n, sqrt_s):
-    """FP32C per-point kernels list the points whose diagram sum cancels
-    beyond what FP32 resolves and recompute them in FP64.  Against the FP64
-    kernel (itself pinned to the oracle), over calls with growing and
-    shrinking N (workspace reuse): relative error <= 1e-4 with the
-    denominator floored at 1e-3 of the median |M|^2 (the bench's reading for
-    configurations that nearly vanish), and <= 3e-4 without the floor."""
+    """FP32C per-point kernels mark the points they cannot vouch for and the
+    FP64 pass recomputes them in place.  Against the FP64 kernel (itself
+    pinned to the oracle), over calls of growing and shrinking N (ragged
+    tails of the fix-up pass's point ranges): plain relative error below 1e-4
+    on every point."""
     from paper_2511_19456_amd.qedx import make_variant
     N = 1 << 16
     u, h = inputs.rambo_inputs(5 + n, n, N, with_helicities=True)
@@ -448,17 +433,42 @@ def test_fp32c_fp64_fixup(n, sqrt_s):
     assert p.info()["fixup"] == 1 and p.info()["fix_kappa"] > 0
     off = _proc(n, "per_point", "fp32c", make_variant(fixup=-1))
     assert off.info()["fixup"] == 0
-    floor = 1e-3 * np.median(np.abs(ref))
-    for M in (N, 1000, 1, 4099, N):
+    worst = 0.0
+    for M in (N, 1000, 1, 4099, 4096, N):
         m = mom[:, :M].contiguous()
         got = p.eval(m, hel[:M].contiguous()).cpu().numpy()
-        err = np.abs(got - ref[:M])
-        assert (err / np.maximum(np.abs(ref[:M]), floor)).max() < 1e-4, M
-        rel = err / np.abs(ref[:M])
-        assert rel.max() < 3e-4, (M, rel.max())
+        assert np.all(got >= 0), M          # no mark left behind
+        rel = np.abs(got - ref[:M]) / np.abs(ref[:M])
+        assert rel.max() < 1e-4, (M, rel.max(), int(np.argmax(rel)))
+        worst = max(worst, rel.max())
     raw = off.eval(mom, hel).cpu().numpy()
     # the pass changes something: without it the worst point is worse
-    assert np.abs(raw / ref - 1.0).max() > rel.max()
+    assert np.abs(raw / ref - 1.0).max() > worst
+
+
+def test_fp32c_two_streams_match_serial():
+    """A process handle is read-only: the same FP32C per-point process
+    evaluated on two streams at once gives bit for bit the results of
+    serial calls (nothing is shared between the calls but the handle)."""
+    n, sqrt_s, N = 5, 20.0, 1 << 17
+    u, h = inputs.rambo_inputs(61, n, N, with_helicities=True)
+    p = _proc(n, "per_point", "fp32c")
+    mom = p.rambo(torch.as_tensor(u, device=DEV), sqrt_s)
+    hel = torch.as_tensor(h.astype(np.int32), device=DEV)
+    a_m, b_m = mom[:, : N // 2].contiguous(), mom[:, N // 2:].contiguous()
+    a_h, b_h = hel[: N // 2].contiguous(), hel[N // 2:].contiguous()
+    ser_a, ser_b = p.eval(a_m, a_h), p.eval(b_m, b_h)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    out_a = torch.full_like(ser_a, float("nan"))
+    out_b = torch.full_like(ser_b, float("nan"))
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            p.eval(a_m, a_h, out=out_a)
+        with torch.cuda.stream(s2):
+            p.eval(b_m, b_h, out=out_b)
+        torch.cuda.synchronize()
+        assert torch.equal(out_a, ser_a) and torch.equal(out_b, ser_b)
 
 
 def test_batch_plan_rejections():
@@ -506,34 +516,27 @@ def test_degenerate_kinematics():
     mm = np.repeat(mom, 16, axis=1)
     pp = _proc(1, "per_point").eval(torch.as_tensor(mm, device=DEV),
                                     torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
-    ref = O.m2(mm, 1, "per_point", hel).numpy()
-    scale = np.repeat(kn / 16.0, 16)
-    assert (np.abs(pp - ref) / np.maximum(np.abs(ref), 1e-3 * scale)).max() < 1e-10
+    ref, kap = per_point_ref(mm, 1, hel)
+    nz = ref > 0          # exact zeros (forbidden configurations at theta = 0, pi) must come out tiny
+    check_fp64(pp[nz], ref[nz], kap[nz], "n=1 along the axis")
+    assert np.all(np.abs(pp[~nz]) <= 1e-20 * np.repeat(kn, 16)[~nz])
     # two photons, the first final-state photon nearly soft (RAMBO energy
-    # -ln(u2 u3) -> 0).  The oracle forms Q.Q - m^2 plainly and loses digits
-    # as the photon softens (its own error ~1e-11 at E_k = 7e-4 sqrt(s),
-    # ~3e-8 at 7e-7); the kernels use the cancellation-free 2 p.K + K^2.  So:
-    # against the oracle at the milder point, and at the extreme point against
-    # the host interpreter of the same graph (same denominators, plain loops).
-    # There the eikonal terms of the diagrams cancel to ~1/E_k of their size,
-    # so two FP64 summation orders already differ by ~1e-9: tolerance 1e-8.
-    from paper_2511_19456_amd.qedx import graph_interpret
-    n, rs, N = 2, 6.0, 8
-    for eps, soft, tol in ((1e-4, 1e-3, 1e-10), (1e-7, 1e-6, 1e-8)):
-        u, h = inputs.rambo_inputs(77, n, N, with_helicities=True)
-        u[4 + 2] = 1.0 - eps
-        u[4 + 3] = 1.0 - eps
-        ref_mom = O.momenta_soa_from_uniforms(u, rs, n)
-        assert float(ref_mom[4 * 3].max()) < soft * rs   # the soft photon's energy
-        m = torch.as_tensor(ref_mom.numpy(), device=DEV)
+    # -ln(u2 u3) -> 0).  The float64 oracle forms Q.Q - m^2 plainly and loses
+    # digits as the photon softens; the stored values come from the same
+    # definition evaluated in x86 extended precision (tests/golden/
+    # near_soft_n2.txt, written by make_golden.py from oracle/ only), with the
+    # float64 momenta the kernels see.
+    import sys
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import read_near_soft
+    n = 2
+    gold = read_near_soft()
+    assert sorted(gold) == [1e-7, 1e-4]
+    for eps, d in sorted(gold.items()):
+        m = torch.as_tensor(d["mom"], device=DEV)
+        assert float(d["mom"][4 * 3].max()) < 10 * eps * 6.0   # the soft photon's energy
         s_got = _proc(n).eval(m).cpu().numpy()
-        p_got = _proc(n, "per_point").eval(m, torch.as_tensor(h.astype(np.int32), device=DEV)).cpu().numpy()
-        if eps == 1e-4:
-            s_ref = O.m2(ref_mom, n, "sum").numpy()
-            p_ref = O.m2(ref_mom, n, "per_point", h).numpy()
-        else:
-            pts = O.soa_to_points(ref_mom).numpy().reshape(N, -1)
-            s_ref = graph_interpret(n, pts, None, enum_mask=(1 << (n + 3)) - 1, reduced=True)
-            p_ref = graph_interpret(n, pts, h, reduced=True)
-        assert np.abs(s_got / s_ref - 1).max() < tol, eps
-        assert (np.abs(p_got - p_ref) / np.maximum(np.abs(p_ref), 1e-3 * s_ref / 32)).max() < tol, eps
+        p_got = _proc(n, "per_point").eval(m, torch.as_tensor(d["hel"].astype(np.int32), device=DEV)).cpu().numpy()
+        assert _rel(s_got, d["sum"]).max() < 1e-10, (eps, _rel(s_got, d["sum"]).max())
+        check_fp64(p_got, d["pp"], d["kappa_terms"], f"near soft eps={eps}")

@@ -38,6 +38,15 @@ template <class T> struct sp4 { cx<T> c[4]; };          // L0 L1 R0 R1
 template <class T> struct pol3 { T e1, e2, e3; };        // eps_vec, eps^0 = 0
 template <class T> struct propq { T qm, qp, q1, q2, mm; };
 
+// Round an FP64 current or polarisation vector to FP32 (one rounding per entry).
+QEDX_HD sp4<float> to_f(const sp4<double>& x) {
+  sp4<float> o;
+  for (int k = 0; k < 4; ++k) o.c[k] = {(float)x.c[k].r, (float)x.c[k].i};
+  return o;
+}
+QEDX_HD pol3<float> to_f(const pol3<double>& e) { return {(float)e.e1, (float)e.e2, (float)e.e3}; }
+QEDX_HD cx<float> to_f(const cx<double>& z) { return {(float)z.r, (float)z.i}; }
+
 // ---------------------------------------------------------------------------
 // 2x2 blocks.  E x and x E for E = [[e3, e1 - i e2], [e1 + i e2, -e3]].
 // y0 = e3 x0 + (e1 - i e2) x1 ; y1 = (e1 + i e2) x0 - e3 x1.     20 FLOPs

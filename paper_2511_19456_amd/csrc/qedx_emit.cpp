@@ -39,6 +39,10 @@ std::string variant_tag(const Variant& v, int n_out, int n_in) {
   return o.str();
 }
 
+std::string pol_lds_type(const Variant& v) {
+  return v.prec == PREC_F64 || !(v.order & 64) ? "double" : "float";
+}
+
 Dag graph_for(const Process& proc, const Variant& v, double* t_build, double* t_reduce) {
   using clk = std::chrono::steady_clock;
   auto t0 = clk::now();
@@ -91,7 +95,21 @@ struct Emitter {
 
   Emitter(const Dag& d_, const Variant& v_) : d(d_), v(v_), pr(d_.proc), done(d_.nodes.size(), 0) {
     T = v.prec == PREC_F64 ? "double" : "float";
+    d1 = v.prec != PREC_F64 && !(v.order & 64);
+    PT = pol_lds_type(v);
   }
+
+  // FP32C: the first vertex and propagator next to each external electron
+  // (U -> V -> S1) are evaluated in FP64 and rounded once.  There
+  // (Qslash + m) eps-slash u(p) = eps-slash kslash u + 2 (eps.p) u for
+  // Q = p - k, so with eps.p ~ 0 and a soft k the product cancels by
+  // ~2E/k; in FP32 that cancellation costs as many digits (likewise
+  // ubar(p') eps-slash (p'-slash + kslash + m) on the other side).  Nodes with an
+  // FP64 copy are named <name>_d.
+  bool d1 = false;
+  std::string PT;  // element type of the per-lane polarisation LDS
+  std::set<int> has_d;
+  std::set<std::pair<int, uint32_t>> qdone_d;
 
   int producer(int i) const {
     const Node& n = d.nodes[i];
@@ -154,10 +172,29 @@ struct Emitter {
     os << ind << "const qx::propq<" << T << "> " << qname(side, mask) << " = qx::prop_from<" << T << ">(m" << pp
        << "_0, m" << pp << "_1, m" << pp << "_2, m" << pp << "_3, " << km << "_0, " << km << "_1, " << km << "_2, "
        << km << "_3, " << (side == 0 ? "1.0" : "-1.0") << ", 1.0);\n";
-    st.flops_per_point += 28;
-    ++st.n_prop;
+    if (!qdone_d.count({side, mask})) {
+      st.flops_per_point += 28;
+      ++st.n_prop;
+    }
     qdone.insert({side, mask});
   }
+
+  // FP64 propagator coefficients (for the FP32C first-step currents)
+  void emitQd(int side, uint32_t mask) {
+    if (qdone_d.count({side, mask})) return;
+    emitK(mask);
+    int pp = side == 0 ? pr.i_ein : pr.i_eout;
+    std::string km = "K" + std::to_string(mask);
+    os << ind << "const qx::propq<double> " << qname(side, mask) << "_d = qx::prop_from<double>(m" << pp << "_0, m"
+       << pp << "_1, m" << pp << "_2, m" << pp << "_3, " << km << "_0, " << km << "_1, " << km << "_2, " << km
+       << "_3, " << (side == 0 ? "1.0" : "-1.0") << ", 1.0);\n";
+    if (!qdone.count({side, mask})) {
+      st.flops_per_point += 28;
+      ++st.n_prop;
+    }
+    qdone_d.insert({side, mask});
+  }
+  std::string name_d(int i) const { return "n" + std::to_string(producer(i)) + "_d"; }
 
   std::string hel_expr(const Node& u) const {
     if (u.hel >= 0) return std::to_string((int)u.hel);
@@ -184,23 +221,28 @@ struct Emitter {
       case Kind::U: {
         int p = n.particle;
         std::string m = "m" + std::to_string(p) + "_";
-        if (p == pr.i_ein)
-          os << ind << "const qx::sp4<" << T << "> " << nm << " = qx::u_in<" << T << ">(" << m << "0, " << m << "1, "
-             << m << "2, " << m << "3, " << hel_expr(n) << ", 1.0);\n";
-        else if (p == pr.i_eout)
-          os << ind << "const qx::sp4<" << T << "> " << nm << " = qx::ubar_out<" << T << ">(" << m << "0, " << m
-             << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", 1.0);\n";
-        else if (slot && pol_lds) {
+        // with d1 the state is built in FP64 (name_d) and rounded for the FP32 graph
+        const std::string TU = d1 ? "double" : T;
+        const std::string nu = d1 ? nm + "_d" : nm;
+        if (p == pr.i_ein || p == pr.i_eout) {
+          os << ind << "const qx::sp4<" << TU << "> " << nu << " = qx::" << (p == pr.i_ein ? "u_in" : "ubar_out") << "<"
+             << TU << ">(" << m << "0, " << m << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", 1.0);\n";
+          if (d1) os << ind << "const qx::sp4<float> " << nm << " = qx::to_f(" << nu << ");\n";
+        } else if (slot && pol_lds) {
           std::string sp = "sp" + std::to_string(slot_of(p));
-          os << ind << "const qx::pol3<" << T << "> " << nm << " = {";
+          os << ind << "const qx::pol3<" << TU << "> " << nu << " = {";
           for (int c = 0; c < 3; ++c)
-            os << (c ? ", " : "") << "qx_pol[(3 * " << sp << " + " << c << ") * " << v.block << " + threadIdx.x]";
+            os << (c ? ", " : "") << (PT != TU ? "(" + TU + ")" : std::string()) << "qx_pol[(3 * " << sp << " + " << c
+               << ") * " << v.block << " + threadIdx.x]";
           os << "};\n";
+          if (d1) os << ind << "const qx::pol3<float> " << nm << " = qx::to_f(" << nu << ");\n";
         } else {
           if (slot) m = "k" + std::to_string(slot_of(p)) + "_";
-          os << ind << "const qx::pol3<" << T << "> " << nm << " = qx::pol<" << T << ">(" << m << "1, " << m << "2, "
+          os << ind << "const qx::pol3<" << TU << "> " << nu << " = qx::pol<" << TU << ">(" << m << "1, " << m << "2, "
              << m << "3, " << hel_expr(n) << ");\n";
+          if (d1) os << ind << "const qx::pol3<float> " << nm << " = qx::to_f(" << nu << ");\n";
         }
+        if (d1) has_d.insert(c);
         st.flops_per_point += 16;
         ++st.n_U;
         break;
@@ -208,16 +250,34 @@ struct Emitter {
       case Kind::V: {
         const Node& ph = d.nodes[producer(n.in[0])];
         bool y = ph.hel == 1;
-        os << ind << "const qx::sp4<" << T << "> " << nm << " = qx::v" << (n.side == 0 ? "L" : "R")
-           << (y ? "_y" : "") << "<" << T << ">(" << name(n.in[1]) << ", " << name(n.in[0]) << ");\n";
+        const Node& cur = d.nodes[producer(n.in[1])];
+        if (d1 && cur.kind == Kind::U && has_d.count(producer(n.in[1])) && has_d.count(producer(n.in[0]))) {
+          // first vertex next to an external electron: FP64, rounded once
+          os << ind << "const qx::sp4<double> " << nm << "_d = qx::v" << (n.side == 0 ? "L" : "R") << (y ? "_y" : "")
+             << "<double>(" << name_d(n.in[1]) << ", " << name_d(n.in[0]) << ");\n";
+          os << ind << "const qx::sp4<float> " << nm << " = qx::to_f(" << nm << "_d);\n";
+          has_d.insert(c);
+        } else {
+          os << ind << "const qx::sp4<" << T << "> " << nm << " = qx::v" << (n.side == 0 ? "L" : "R")
+             << (y ? "_y" : "") << "<" << T << ">(" << name(n.in[1]) << ", " << name(n.in[0]) << ");\n";
+        }
         st.flops_per_point += y ? 24 : 40;
         ++st.n_V;
         break;
       }
       case Kind::S1: {
-        emitQ(n.side, n.mask);
-        os << ind << "const qx::sp4<" << T << "> " << nm << " = qx::s" << (n.side == 0 ? "L" : "R") << "<" << T
-           << ">(" << name(n.in[0]) << ", " << qname(n.side, n.mask) << ");\n";
+        if (d1 && d.nodes[producer(n.in[0])].kind == Kind::V && has_d.count(producer(n.in[0]))) {
+          // propagator after the first vertex: FP64 on the FP64 current, rounded once
+          emitQd(n.side, n.mask);
+          os << ind << "const qx::sp4<double> " << nm << "_d = qx::s" << (n.side == 0 ? "L" : "R") << "<double>("
+             << name_d(n.in[0]) << ", " << qname(n.side, n.mask) << "_d);\n";
+          os << ind << "const qx::sp4<float> " << nm << " = qx::to_f(" << nm << "_d);\n";
+          has_d.insert(c);
+        } else {
+          emitQ(n.side, n.mask);
+          os << ind << "const qx::sp4<" << T << "> " << nm << " = qx::s" << (n.side == 0 ? "L" : "R") << "<" << T
+             << ">(" << name(n.in[0]) << ", " << qname(n.side, n.mask) << ");\n";
+        }
         st.flops_per_point += 56;
         ++st.n_S1;
         break;
@@ -265,15 +325,20 @@ struct Emitter {
     if (v.prec == PREC_F64) {
       os << ind << "qx::dot_acc<double>(A" << acc << ", " << B << ", " << name(ops.first) << ");\n";
       st.flops_per_point += 32;
-    } else if (abs_sum) {
-      os << ind << "{ const qx::cx<float> x_ = qx::dot<float>(" << B << ", " << name(ops.first)
-         << "); qx::comp_acc<float>(A" << acc << ", C" << acc << ", x_); S" << acc
-         << " = fmaf(x_.r, x_.r, fmaf(x_.i, x_.i, S" << acc << ")); }\n";
-      st.flops_per_point += 30 + 14 + 2;
     } else {
-      os << ind << "qx::comp_acc<float>(A" << acc << ", C" << acc << ", qx::dot<float>(" << B << ", "
-         << name(ops.first) << "));\n";
-      st.flops_per_point += 30 + 14;
+      // a join of two FP64 first-step currents (one photon on each side):
+      // the dot in FP64 too, the diagram value rounded once
+      std::string x = "qx::dot<float>(" + B + ", " + name(ops.first) + ")";
+      if (n.kind == Kind::Dot && has_d.count(producer(ops.second)) && has_d.count(producer(ops.first)))
+        x = "qx::to_f(qx::dot<double>(" + name_d(ops.second) + ", " + name_d(ops.first) + "))";
+      if (abs_sum) {
+        os << ind << "{ const qx::cx<float> x_ = " << x << "; qx::comp_acc<float>(A" << acc << ", C" << acc
+           << ", x_); S" << acc << " = fmaf(x_.r, x_.r, fmaf(x_.i, x_.i, S" << acc << ")); }\n";
+        st.flops_per_point += 30 + 14 + 2;
+      } else {
+        os << ind << "qx::comp_acc<float>(A" << acc << ", C" << acc << ", " << x << ");\n";
+        st.flops_per_point += 30 + 14;
+      }
     }
     ++st.n_dot;
     fence(2);
@@ -333,6 +398,8 @@ struct Emitter {
     std::fill(done.begin(), done.end(), 0);
     kdone.clear();
     qdone.clear();
+    qdone_d.clear();
+    has_d.clear();
     return outer;
   }
   void close_block(const std::string& outer) {
@@ -455,7 +522,7 @@ struct Emitter {
     if (pol_lds)
       for (int a = 0; a < P; ++a) {
         int pp = pr.photon_particle[a];
-        os << ind << "{ const qx::pol3<" << T << "> e_ = qx::pol<" << T << ">(mom[" << (4 * pp + 1) << " * N + ptc], mom["
+        os << ind << "{ const qx::pol3<" << PT << "> e_ = qx::pol<" << PT << ">(mom[" << (4 * pp + 1) << " * N + ptc], mom["
            << (4 * pp + 2) << " * N + ptc], mom[" << (4 * pp + 3) << " * N + ptc], (int)((hc >> " << pp << ") & 1u));";
         for (int c = 0; c < 3; ++c)
           os << " qx_pol[" << (3 * pp + c) * v.block << " + threadIdx.x] = e_.e" << (c + 1) << ";";
@@ -474,6 +541,8 @@ struct Emitter {
     std::fill(done.begin(), done.end(), 0);
     kdone.clear();
     qdone.clear();
+    qdone_d.clear();
+    has_d.clear();
     double f0 = st.flops_per_point;
     bool was_local = (v.order & 4) != 0;
     (void)was_local;
@@ -973,7 +1042,7 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     if (e.lds_slots > 0)
       decl = "  __shared__ " + e.T + " qx_lds[" + std::to_string(e.lds_slots * 8 * v.block) + "];\n";
     if (e.pol_lds)
-      decl += "  __shared__ " + e.T + " qx_pol[" + std::to_string(3 * d.proc.npart * v.block) + "];\n";
+      decl += "  __shared__ " + e.PT + " qx_pol[" + std::to_string(3 * d.proc.npart * v.block) + "];\n";
     size_t at = src.find(lds_mark);
     src.replace(at, lds_mark.size(), decl);
   }
@@ -1252,7 +1321,7 @@ std::string emit_body_function(const Dag& d, const Variant& v, const std::string
   }
   os << "static __device__ double " << fname
      << "(const double* __restrict__ mom, long long N, long long ptc, unsigned hrt_in"
-     << (e.pol_lds ? ", " + e.T + "* __restrict__ qx_pol" : std::string()) << (v.fixup ? ", int& fixflag, double fix_kappa" : "")
+     << (e.pol_lds ? ", " + e.PT + "* __restrict__ qx_pol" : std::string()) << (v.fixup ? ", int& fixflag, double fix_kappa" : "")
      << ")\n{\n";
   if (!e.local() && !e.slot) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";

@@ -102,6 +102,11 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
 std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* st,
                                bool pol_param = false);
 
+// Element type ("double" or "float") of the per-lane photon polarisation LDS
+// of slot-loop kernels and bodies: FP64 unless an FP32C variant turns off its
+// FP64 first-step currents (order flag 64).
+std::string pol_lds_type(const Variant& v);
+
 // The device header text (inlined into every generated unit).
 const std::string& device_header_text();
 

@@ -362,6 +362,11 @@ static qed_status make_variant_shape(int n, int nin, qed_hel_mode mode, qed_prec
       return fail(QED_ERR_INVALID_ARG, "lane_bits/loop_bits apply to SUM mode only");
     }
   }
+  // FP32C with one photon on the e-_in side of every join: the join's
+  // propagator goes onto that side, where it follows the first vertex and is
+  // evaluated in FP64 with it (the product next to the external electron can
+  // cancel; see the emitter's first-step currents)
+  v.join_side = (v.prec == PREC_F32C && v.split == 1) ? 0 : 1;
   if (v.block % 64 || v.block < 64 || v.block > 1024) return fail(QED_ERR_INVALID_ARG, "block must be 64..1024, multiple of 64");
   if (v.split < 1 || v.split > P - 1) return fail(QED_ERR_INVALID_ARG, "split must be in 1..(photons - 1)");
   if (__builtin_popcount(v.lane_mask) > 6) return fail(QED_ERR_INVALID_ARG, "at most 6 lane bits");

@@ -59,3 +59,41 @@ def check_fp64(got, ref, kappa, what: str = "", rel: float = REL_FP64):
         raise AssertionError(f"{what}: {int((~ok).sum())} of {len(ok)} points outside the bound; worst point {i}: "
                              f"got {got[i]!r} ref {ref[i]!r} rel {err[i] / abs(ref[i]):.3e} kappa {kappa[i]:.3e}")
     return float((err / np.abs(ref)).max()) if len(ref) else 0.0
+
+
+def rambo_boost_gamma(u, n: int):
+    """Per point, the boost factor gamma = Q^0 / M of RAMBO's massless stage
+    (the isotropic momenta q_j drawn from the uniforms sum to Q, M^2 = Q.Q).
+
+    RAMBO forms M from Q^0^2 - |Q|^2, which cancels by ~gamma^2, and its
+    boost adds terms each ~gamma^2 larger than their sum; rounding in any
+    float64 evaluation of the map (the device's and the oracle's alike) is
+    therefore amplified by up to ~gamma^4.  Used only to scale tolerances."""
+    u = np.asarray(u, dtype=np.float64)
+    Q = np.zeros((4, u.shape[1]))
+    for j in range(n + 1):
+        c = 2.0 * u[4 * j] - 1.0
+        ph = 2.0 * np.pi * u[4 * j + 1]
+        q0 = -np.log(u[4 * j + 2] * u[4 * j + 3])
+        st = np.sqrt(np.maximum(0.0, 1.0 - c * c))
+        Q += np.stack([q0, q0 * st * np.cos(ph), q0 * st * np.sin(ph), q0 * c])
+    M = np.sqrt(np.maximum(Q[0] ** 2 - (Q[1:] ** 2).sum(0), 1e-300))
+    return Q[0] / M
+
+
+def rambo_allowed(u, n: int, sqrt_s: float):
+    """Allowed |device - oracle| per point for RAMBO momenta: 1e-12 sqrt(s),
+    or 16 eps gamma^4 sqrt(s) where the massless boost is large."""
+    g = rambo_boost_gamma(u, n)
+    return sqrt_s * np.maximum(1e-12, 16.0 * EPS64 * g ** 4)
+
+
+def check_rambo(mom_dev, ref_mom, u, n: int, sqrt_s: float, what: str = ""):
+    """Assert device RAMBO momenta [rows][N] against the oracle's, per point."""
+    d = np.abs(np.asarray(mom_dev) - np.asarray(ref_mom)).max(axis=0)
+    lim = rambo_allowed(u, n, sqrt_s)
+    ok = d <= lim
+    if not ok.all():
+        i = int(np.argmax(d / lim))
+        raise AssertionError(f"{what}: RAMBO momenta off at {int((~ok).sum())} points; worst {i}: "
+                             f"diff {d[i]:.3e} allowed {lim[i]:.3e} gamma {rambo_boost_gamma(u[:, i:i + 1], n)[0]:.2f}")

@@ -63,27 +63,29 @@ def test_long_double_agrees_with_float64_oracle(n, rs):
 
 
 def test_near_soft_golden_values():
-    """The stored near-soft values: at the milder point (soft energy 7e-4
-    sqrt(s)) the float64 oracle agrees to 1e-11; at the extreme point (7e-7)
-    the float64 oracle's plain Q.Q - m^2 loses ~9 digits, the long-double
-    values do not; both obey the eikonal limit of the one-photon process
-    (Sec. I-D propagator near its pole) to first order in the soft energy."""
-    from make_golden import near_soft_points, read_near_soft
+    """The stored near-soft values, at exact kinematics (dyadic, on shell,
+    conserving): the generator's points are reproduced bit for bit; at the
+    milder point (soft energy ~2^-13) the float64 oracle agrees to 1e-11; at
+    the extreme point (~2^-23) its plain Q.Q - m^2 loses digits and the
+    long-double values do not; both obey the eikonal limit of the one-photon
+    process (Sec. I-D propagator near its pole) to first order in the soft
+    energy."""
+    from make_golden import SOFT_SHIFTS, near_soft_points, read_near_soft
     d = read_near_soft()
-    assert set(d) == {1e-4, 1e-7}
-    for eps, r in d.items():
-        mom, h = near_soft_points(eps)
+    assert sorted(d) == sorted(SOFT_SHIFTS)
+    for shift, r in d.items():
+        mom, h = near_soft_points(shift)
         assert np.array_equal(mom, r["mom"]) and np.array_equal(h, r["hel"])
         s64 = O.m2(r["mom"], 2, "sum").numpy()
         e64 = np.abs(s64 / r["sum"] - 1).max()
-        if eps == 1e-4:
+        if shift == 13:
             assert e64 < 1e-11
         else:
-            assert 1e-11 < e64 < 1e-7   # the float64 oracle's denominator cancellation
+            assert 1e-12 < e64 < 1e-6, e64   # the float64 oracle's denominator cancellation
         # eikonal factor times the one-photon helicity sum at the reduced kinematics
         pts = O.soa_to_points(r["mom"]).numpy()
         p, pp, ks = pts[:, 0], pts[:, 2], pts[:, 3]
-        e0 = ks[:, 0] / 6.0
+        e0 = ks[:, 0] / pp[:, 0]
         dot = lambda a, b: a[:, 0] * b[:, 0] - (a[:, 1:] * b[:, 1:]).sum(1)
         eik = 2 * dot(p, pp) / (dot(p, ks) * dot(pp, ks)) - 1 / dot(p, ks) ** 2 - 1 / dot(pp, ks) ** 2
         # one-photon process e-(p) gamma(k) -> e-(p'') gamma(k'_2), p'' = p' + k_soft
@@ -91,4 +93,4 @@ def test_near_soft_golden_values():
         # (p'' is off shell by 2 p'.k_soft, an O(soft energy) change like the limit's own)
         n1 = O.m2(np.ascontiguousarray(red.transpose(1, 2, 0).reshape(16, -1)), 1, "sum").numpy()
         ratio = r["sum"] / (eik * n1)
-        assert np.all(np.abs(ratio - 1) < 50 * e0.max()), (eps, ratio)
+        assert np.all(np.abs(ratio - 1) < 50 * e0.max()), (shift, ratio, e0.max())

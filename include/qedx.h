@@ -192,6 +192,21 @@ qed_status qed_eval_grad(const qed_process* p, const double* uniforms, double sq
  * the largest chunk); 0 for processes with the fused gradient kernel. */
 qed_status qed_eval_grad_workspace_size(const qed_process* p, int64_t N, int64_t* bytes);
 
+/* qed_eval_grad without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * qed_eval_grad; the n = 4 split gradient runs its chunks through a fixed
+ * scratch array the library holds on every GPU it runs on (256 MiB per
+ * device, kept until the process ends), which caps a chunk at 2^16 points
+ * at n = 4; any N runs, in ceil(N / chunk) passes.  A process whose 64-point
+ * chunk would not fit is UNSUPPORTED.  The call allocates nothing and does
+ * not synchronise.  All calls on one GPU share that GPU's scratch and the
+ * scratch keeps the last call's contents (the kernels initialise what they
+ * read): calls that overlap on one GPU (several streams or threads) race and
+ * must be serialised by the caller. */
+qed_status qed_eval_grad_noalloc(const qed_process* p, const double* uniforms, double sqrt_s, const uint32_t* hel,
+                                 int64_t N, double* out_logm2, double* out_grad, void* stream);
+
 /* Mixed-process batches: segments of different processes evaluated by one
  * persistent kernel launch (captured in a HIP graph at plan creation).
  * All processes of one plan must share the precision (and, for FP32C, the

@@ -63,6 +63,8 @@ SIGNATURES = {
     "qed_eval_grad": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
                               c_int64, c_void_p]),
     "qed_eval_grad_workspace_size": (c_int, [c_void_p, c_int64, ctypes.POINTER(c_int64)]),
+    "qed_eval_grad_noalloc": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_int64, c_void_p, c_void_p,
+                                      c_void_p]),
     "qed_batch_plan_create": (c_int, [ctypes.POINTER(QedSegment), c_int, c_int, ctypes.POINTER(c_void_p)]),
     "qed_batch_launch": (c_int, [c_void_p, c_void_p]),
     "qed_batch_plan_destroy": (c_int, [c_void_p]),

@@ -85,9 +85,30 @@ def _link(out, objs, extra):
 HOST_EXTRA_FLAGS = os.environ.get("QEDX_HOST_FLAGS", "").split()
 
 
+# the library's one HIP-compiled unit: the per-device scratch array of the
+# allocation-free entry point (a __device__ symbol needs the HIP compiler)
+HIP_SOURCES = ["qedx_scratch.hip"]
+
+
+def _compile_hip_objects(sources, verbose):
+    objs = []
+    for s in sources:
+        o = os.path.join(CSRC, "_build", s.replace(".hip", ".o"))
+        os.makedirs(os.path.dirname(o), exist_ok=True)
+        cmd = [os.path.join(ROCM, "bin", "hipcc"), "-std=c++17", "-O2", "-fPIC", "--offload-arch=gfx950",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-c", os.path.join(CSRC, s), "-o", o]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("compile failed: " + " ".join(cmd) + "\n" + r.stderr)
+        if verbose and r.stderr:
+            print(r.stderr, file=sys.stderr)
+        objs.append(o)
+    return objs
+
+
 def build_library(verbose: bool = False) -> None:
     embed_headers()
-    _link(LIB, _compile_objects(HOST_SOURCES, verbose), [])
+    _link(LIB, _compile_objects(HOST_SOURCES, verbose) + _compile_hip_objects(HIP_SOURCES, verbose), [])
     # the probe library resolves the code-object cache and error reporting
     # from libqedx.so next to it
     _link(PROBE_LIB, _compile_objects(PROBE_SOURCES, verbose), [f"-L{PKG}", "-lqedx", "-Wl,-rpath,$ORIGIN"])

@@ -55,14 +55,7 @@ qed_status get_code_object(const std::string& tag, const std::string& src, std::
 std::string cache_dir();
 // Kernel shape the library uses for (n, mode, prec) when the caller gives none.
 qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, qedx::Variant& v);
-// Gradient pieces shared by qed_eval_grad and its allocation-free variant:
-// argument checks, the fused kernel (n <= 3), and the split kernels over
-// chunks of C points through a workspace of C * grad_ws_per_point bytes.
-int64_t grad_ws_per_point(const qed_process* p);
-qed_status grad_check(const qed_process* p, const double* uniforms, double sqrt_s, const uint32_t* hel, int64_t N,
-                      double* out_logm2, double* out_grad);
+// Launch of the fused gradient kernel (n <= 3).
 qed_status grad_fused(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N, double* out_logm2,
                       double* out_grad, void* stream);
-qed_status grad_split_chunks(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N,
-                             double* out_logm2, double* out_grad, double* ws, int64_t C, void* stream);
 }  // namespace qedx_rt

@@ -31,6 +31,7 @@
 #include "qedx_dag.hpp"
 #include "qedx_emit.hpp"
 #include "qedx_internal.hpp"
+#include "qedx_scratch.hpp"
 #include "qedx_kernels.hpp"
 
 extern char** environ;
@@ -635,11 +636,6 @@ extern "C" qed_status qed_rambo(const qed_process* p, const double* uniforms, do
   return launch(p->f_rambo, N, 256, stream, args);
 }
 
-namespace qedx_rt {
-qed_status grad_fused(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N, double* out_logm2,
-                      double* out_grad, void* stream);
-}
-
 // Split gradient: bytes of workspace per point (momenta and momentum
 // gradient [4 npart] each, amplitudes [2 H], 1/|M|^2) and the largest chunk
 // of points one pass takes (a power of two, at most 2^20 and 320 MB).
@@ -722,6 +718,27 @@ extern "C" qed_status qed_eval_grad(const qed_process* p, const double* uniforms
   if ((uintptr_t)workspace % 8) return fail(QED_ERR_INVALID_ARG, "workspace must be 8-byte aligned");
   const int64_t C = std::min(N, std::min(workspace_bytes / per_pt, grad_max_chunk(p)));
   return grad_split_chunks(p, uniforms, sqrt_s, N, out_logm2, out_grad, (double*)workspace, C, stream);
+}
+
+// The same gradient with the library's fixed per-device scratch in place of
+// the caller's workspace: no allocation, no synchronisation.  The scratch
+// bounds the chunk of points per pass, not N.
+extern "C" qed_status qed_eval_grad_noalloc(const qed_process* p, const double* uniforms, double sqrt_s,
+                                            const uint32_t* hel, int64_t N, double* out_logm2, double* out_grad,
+                                            void* stream) {
+  qed_status s = grad_check(p, uniforms, sqrt_s, hel, N, out_logm2, out_grad);
+  if (s || N == 0) return s;
+  if (!p->grad_split) return qedx_rt::grad_fused(p, uniforms, sqrt_s, N, out_logm2, out_grad, stream);
+  const int64_t per_pt = grad_ws_per_point(p);
+  if (per_pt * 64 > qedx_rt::kScratchBytes)
+    return fail(QED_ERR_UNSUPPORTED, "a 64-point chunk of this process needs " + std::to_string(per_pt * 64) +
+                                         " bytes, more than the " + std::to_string(qedx_rt::kScratchBytes) +
+                                         "-byte scratch");
+  void* ws = nullptr;
+  hipError_t e = qedx_rt::scratch_address(&ws);
+  if (e != hipSuccess) return fail(QED_ERR_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+  const int64_t C = std::min(N, std::min(qedx_rt::kScratchBytes / per_pt, grad_max_chunk(p)));
+  return grad_split_chunks(p, uniforms, sqrt_s, N, out_logm2, out_grad, (double*)ws, C, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -832,20 +849,11 @@ qed_status get_code_object(const std::string& tag, const std::string& src, std::
   return ::get_code_object(tag, src, co, meta, hit, ms);
 }
 std::string cache_dir() { return cache_dir_str(); }
-int64_t grad_ws_per_point(const qed_process* p) { return ::grad_ws_per_point(p); }
-qed_status grad_check(const qed_process* p, const double* uniforms, double sqrt_s, const uint32_t* hel, int64_t N,
-                      double* out_logm2, double* out_grad) {
-  return ::grad_check(p, uniforms, sqrt_s, hel, N, out_logm2, out_grad);
-}
 qed_status grad_fused(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N, double* out_logm2,
                       double* out_grad, void* stream) {
   long long n = (long long)N;
   void* args[] = {(void*)&uniforms, (void*)&sqrt_s, (void*)&n, (void*)&out_logm2, (void*)&out_grad};
   return launch(p->f_grad, N * (int64_t)p->grad_lanes, p->grad_block, stream, args);
-}
-qed_status grad_split_chunks(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N,
-                             double* out_logm2, double* out_grad, double* ws, int64_t C, void* stream) {
-  return ::grad_split_chunks(p, uniforms, sqrt_s, N, out_logm2, out_grad, ws, C, stream);
 }
 qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, qedx::Variant& v) {
   return make_variant(n, 1, mode, prec, nullptr, v);

@@ -169,6 +169,22 @@ class QedProcess:
                                   _ptr(workspace), nbytes, _stream()))
         return val, grad
 
+    def eval_grad_noalloc(self, uniforms: torch.Tensor, sqrt_s: float, out: tuple):
+        """eval_grad through qed_eval_grad_noalloc: the library's fixed
+        per-device scratch instead of a workspace; `out` = (val [N],
+        grad [4(n+1), N]) preallocated float64 device tensors.  Calls that
+        overlap on one GPU share the scratch and must be serialised."""
+        _dev_tensor(uniforms, torch.float64, 4 * (self.n + 1), "uniforms")
+        N = uniforms.shape[1]
+        val, grad = out
+        _dev_tensor(grad, torch.float64, 4 * (self.n + 1), "grad")
+        if val.shape != (N,) or val.dtype != torch.float64 or not val.is_cuda or not val.is_contiguous() \
+                or grad.shape[1] != N:
+            raise ValueError("out must be (float64 [N], float64 [4(n+1), N]) contiguous device tensors")
+        check(lib().qed_eval_grad_noalloc(self._h, _ptr(uniforms), float(sqrt_s), None, N, _ptr(val), _ptr(grad),
+                                          _stream()))
+        return val, grad
+
 
 class QedLogM2(torch.autograd.Function):
     """log|M|^2 (helicity sum) of RAMBO points as a differentiable function of

@@ -54,6 +54,13 @@ qed_status qed_emit_source(int n, qed_hel_mode mode, qed_precision prec, const q
  * with float32 value sizes if fp32 != 0. */
 qed_status qed_graph_metrics(int n, int n_in, uint32_t enum_mask, int split, int reduced, int fp32,
                              double* c_dag, double* d_dag);
+/* Forward C(DAG) (as qed_graph_metrics, float64) and the reverse-mode cost of
+ * the same graph (FLOPs per point the adjoint sweep of log sum |A|^2 adds:
+ * per node the vector-Jacobian products of the device functions), for the
+ * process with one incoming photon; the gradient's algorithmic FLOPs are
+ * their sum. */
+qed_status qed_graph_adjoint_metrics(int n, uint32_t enum_mask, int split, int reduced, double* c_fwd,
+                                     double* c_adj);
 /* Host references of the gradient pieces (no GPU), for tests:
  * qed_graph_grad_interpret: F = log(sum over all configurations of |A|^2) and
  * dF/dmom by a reverse sweep over the graph in float64.  mom host [N][4(n+3)]

@@ -89,6 +89,8 @@ SIGNATURES = {
                                   ctypes.POINTER(c_int64)]),
     "qed_graph_metrics": (c_int, [c_int, c_int, c_uint32, c_int, c_int, c_int, ctypes.POINTER(c_double),
                                   ctypes.POINTER(c_double)]),
+    "qed_graph_adjoint_metrics": (c_int, [c_int, c_uint32, c_int, c_int, ctypes.POINTER(c_double),
+                                          ctypes.POINTER(c_double)]),
 }
 
 # the measurement library (include/qedx_probe.h)

@@ -675,6 +675,57 @@ double compute_effort(const Dag& d, bool fp32) {
   return c + kPropSetupFlops * (double)props.size();
 }
 
+// Reverse-mode cost of the same graph (the adjoint sweep of F = log sum |A|^2
+// that a gradient adds to the forward evaluation), per node, following the
+// vector-Jacobian products of qedx_device.h: V its forward map on the
+// adjoint (40 or 24) plus the polarisation gradient 60; S1 56 plus the
+// propagator-coefficient gradient 69; external spinor 96, polarisation
+// vector 40; 2 per amplitude for its seed conj(A)/|M|^2; 8 per extra
+// consumer of a current (adjoint accumulation); 50 per distinct propagator
+// set-up (its gradient into the electron momentum and the photon sum).
+// Dots: the dots of one amplitude within one photon partition pair every
+// row leaf with every column leaf, so their adjoint is taken from the two
+// leaf sums: 8 per leaf for the sums and 2 x 32 for the two seeds, in place
+// of 2 x 32 per dot.
+double adjoint_effort(const Dag& d) {
+  double c = 0.0;
+  std::map<std::pair<int, uint32_t>, int> props;
+  // (column leaf's photon set, amplitude) -> distinct row and column leaves
+  std::map<std::pair<uint32_t, int>, std::pair<std::set<int>, std::set<int>>> groups;
+  auto prod = [&](int x) { return d.nodes[x].kind == Kind::Data ? d.nodes[x].in[0] : x; };
+  for (size_t i = 0; i < d.nodes.size(); ++i) {
+    const Node& n = d.nodes[i];
+    if (n.kind == Kind::Dot) {
+      int a = prod(n.in[0]), b = prod(n.in[1]);
+      if (d.nodes[a].side != 0) std::swap(a, b);
+      int sum = n.out.empty() ? -1 : d.nodes[n.out[0]].out.empty() ? -1 : d.nodes[n.out[0]].out[0];
+      auto& g = groups[{d.nodes[a].mask, sum}];
+      g.first.insert(b);
+      g.second.insert(a);
+    }
+    switch (n.kind) {
+      case Kind::U: {
+        bool ph = n.particle != d.proc.i_ein && n.particle != d.proc.i_eout;
+        c += ph ? 40.0 : 96.0;
+        break;
+      }
+      case Kind::V: c += (photon_state_is_y(d, n) ? 24.0 : 40.0) + 60.0; break;
+      case Kind::S1: c += 56.0 + 69.0; props[{n.side, n.mask}] = 1; break;
+      case Kind::S2: c += 56.0 + 69.0 + 64.0; props[{1, d.nodes[n.in[1]].mask}] = 1; break;
+      case Kind::Sum: c += 2.0; break;
+      default: break;
+    }
+    if (n.kind == Kind::Data && !n.in.empty() && n.out.size() > 1) {
+      const Node& src = d.nodes[n.in[0]];
+      if (src.kind == Kind::V || src.kind == Kind::S1 || src.kind == Kind::Add ||
+          (src.kind == Kind::U && (src.particle == d.proc.i_ein || src.particle == d.proc.i_eout)))
+        c += 8.0 * (double)(n.out.size() - 1);
+    }
+  }
+  for (auto& g : groups) c += 64.0 + 8.0 * (double)(g.second.first.size() + g.second.second.size());
+  return c + 50.0 * (double)props.size();
+}
+
 double data_transfer(const Dag& d, bool fp32) {
   double t = 0.0;
   for (size_t i = 0; i < d.nodes.size(); ++i)

@@ -123,6 +123,9 @@ double node_bytes(const Dag& d, int i, bool fp32);
 // C(DAG), D(DAG), I(DAG) (App. B, graph metrics).
 double compute_effort(const Dag& d, bool fp32);
 double data_transfer(const Dag& d, bool fp32);
+// Reverse-mode (adjoint) cost of the graph in FLOPs per point, on top of
+// compute_effort's forward cost.
+double adjoint_effort(const Dag& d);
 
 // Host interpreter in double precision: value of the exit (sum over the
 // enumerated configurations of |A|^2) for one point.  mom[4*particle + mu];

@@ -197,18 +197,16 @@ template <class T> QEDX_HD void comp_acc(cx<T>& s, cx<T>& c, const cx<T>& x) {
 template <class T> QEDX_HD sp4<T> u_in(double E, double px, double py, double pz, int s, double m) {
   double c = E + m;
   double nrm = 1.0 / sqrt(2.0 * c);
+  // spin 0: (c - pz, -px - i py, c + pz, px + i py) nrm
+  // spin 1: (-px + i py, c + pz, px - i py, c - pz) nrm
+  // (selects, not branches: the spin may be a run-time lane bit)
+  const double a = (c - pz) * nrm, b = (c + pz) * nrm, x = px * nrm, y = py * nrm;
+  const bool up = s == 0;
   sp4<T> o;
-  if (s == 0) {
-    o.c[0] = {T((c - pz) * nrm), T(0)};
-    o.c[1] = {T(-px * nrm), T(-py * nrm)};
-    o.c[2] = {T((c + pz) * nrm), T(0)};
-    o.c[3] = {T(px * nrm), T(py * nrm)};
-  } else {
-    o.c[0] = {T(-px * nrm), T(py * nrm)};
-    o.c[1] = {T((c + pz) * nrm), T(0)};
-    o.c[2] = {T(px * nrm), T(-py * nrm)};
-    o.c[3] = {T((c - pz) * nrm), T(0)};
-  }
+  o.c[0] = {T(up ? a : -x), T(up ? 0.0 : y)};
+  o.c[1] = {T(up ? -x : b), T(up ? -y : 0.0)};
+  o.c[2] = {T(up ? b : x), T(up ? 0.0 : -y)};
+  o.c[3] = {T(up ? x : a), T(up ? y : 0.0)};
   return o;
 }
 template <class T> QEDX_HD sp4<T> ubar_out(double E, double px, double py, double pz, int s, double m) {
@@ -227,30 +225,22 @@ template <class T> QEDX_HD pol3<T> pol(double kx, double ky, double kz, int lam)
   double kt2 = kx * kx + ky * ky;
   double kt = sqrt(kt2);
   double kk = sqrt(kt2 + kz * kz);
-  double cf, sf, ct, st;
-  if (kt > 0.0) {
-    double ikt = 1.0 / kt;
-    double ikk = 1.0 / kk;
-    cf = kx * ikt;
-    sf = ky * ikt;
-    ct = kz * ikk;
-    st = kt * ikk;
-  } else {
-    cf = 1.0;
-    sf = 0.0;
-    ct = kz > 0.0 ? 1.0 : (kz < 0.0 ? -1.0 : 0.0);
-    st = 0.0;
-  }
+  // k_T = 0 (along the z axis): phi = 0, cos theta = sign kz.  Written with
+  // selects rather than branches so the surrounding straight-line code stays
+  // one basic block.
+  const bool flat = !(kt > 0.0);
+  const double ikt = 1.0 / (flat ? 1.0 : kt);
+  const double ikk = 1.0 / (flat ? 1.0 : kk);
+  const double sgn = kz > 0.0 ? 1.0 : (kz < 0.0 ? -1.0 : 0.0);
+  const double cf = flat ? 1.0 : kx * ikt;
+  const double sf = flat ? 0.0 : ky * ikt;
+  const double ct = flat ? sgn : kz * ikk;
+  const double st = flat ? 0.0 : kt * ikk;
+  const bool x = lam == 0;
   pol3<T> e;
-  if (lam == 0) {
-    e.e1 = T(ct * cf);
-    e.e2 = T(ct * sf);
-    e.e3 = T(-st);
-  } else {
-    e.e1 = T(-sf);
-    e.e2 = T(cf);
-    e.e3 = T(0);
-  }
+  e.e1 = T(x ? ct * cf : -sf);
+  e.e2 = T(x ? ct * sf : cf);
+  e.e3 = T(x ? -st : 0.0);
   return e;
 }
 
@@ -425,8 +415,15 @@ QEDX_HD void pol_vjp(double kx, double ky, double kz, int lam, const pol3<double
   double kt = sqrt(kt2);
   double kk2 = kt2 + kz * kz;
   double kk = sqrt(kk2);
-  g[0] = g[1] = g[2] = 0.0;
-  if (!(kt > 0.0)) return;  // measure-zero direction; derivative not defined
+  // along the z axis (measure zero) the derivative is not defined: zero,
+  // with selects instead of an early return (one basic block)
+  const bool flat = !(kt > 0.0);
+  if (flat) {
+    kt = 1.0;
+    kt2 = 1.0;
+    kk = 1.0;
+    kk2 = 1.0;
+  }
   double cf = kx / kt, sf = ky / kt, ct = kz / kk, st = kt / kk;
   double kt3 = kt2 * kt, kk3 = kk2 * kk;
   // partial derivatives of cf, sf, ct, st
@@ -435,10 +432,10 @@ QEDX_HD void pol_vjp(double kx, double ky, double kz, int lam, const pol3<double
   double dct[3] = {-kz * kx / kk3, -kz * ky / kk3, kt2 / kk3};
   double dst[3] = {cf * kz * kz / kk3, sf * kz * kz / kk3, -kt * kz / kk3};
   for (int j = 0; j < 3; ++j) {
-    if (lam == 0)  // (ct cf, ct sf, -st)
-      g[j] = ge.e1 * (dct[j] * cf + ct * dcf[j]) + ge.e2 * (dct[j] * sf + ct * dsf[j]) - ge.e3 * dst[j];
-    else  // (-sf, cf, 0)
-      g[j] = -ge.e1 * dsf[j] + ge.e2 * dcf[j];
+    // lam 0: eps = (ct cf, ct sf, -st); lam 1: (-sf, cf, 0)
+    const double gx = ge.e1 * (dct[j] * cf + ct * dcf[j]) + ge.e2 * (dct[j] * sf + ct * dsf[j]) - ge.e3 * dst[j];
+    const double gy = -ge.e1 * dsf[j] + ge.e2 * dcf[j];
+    g[j] = flat ? 0.0 : (lam == 0 ? gx : gy);
   }
 }
 // Gradient through prop_from: given g over (qm, qp, q1, q2, mm), accumulate

@@ -613,6 +613,24 @@ struct Emitter {
     return "qx_gm[" + std::to_string((4 * p + mu) * v.block) + " + threadIdx.x]";
   }
 
+  // Propagator-coefficient gradients accumulated per distinct propagator
+  // (side, photon set) in per-lane LDS, across every iteration of the
+  // kernel, and mapped to momentum gradients once at its end (the map
+  // gq -> (gp, gK) is linear and depends on the momenta only).  Keeps the
+  // propagator kinematics out of the registers of the adjoint walk.
+  bool gq_in_lds = false;
+  std::map<std::pair<int, uint32_t>, int> gq_slot;
+  int gq_index(int side, uint32_t mask) {
+    auto it = gq_slot.find({side, mask});
+    if (it != gq_slot.end()) return it->second;
+    int k = (int)gq_slot.size();
+    gq_slot[{side, mask}] = k;
+    return k;
+  }
+  std::string gqref(int slot, int c) const {
+    return "qx_gq[" + std::to_string((5 * slot + c) * v.block) + " + threadIdx.x]";
+  }
+
   void collect_block(const std::vector<int>& dk) {
     blk.clear();
     cons.clear();
@@ -659,6 +677,25 @@ struct Emitter {
     os << ind << "}\n";
   }
 
+  // momentum gradients of every accumulated propagator (end of the kernel;
+  // momenta m<p>_<mu> in scope)
+  void flush_gq() {
+    for (auto& kv : gq_slot) {
+      const int side = kv.first.first;
+      const uint32_t mask = kv.first.second;
+      os << ind << "{\n";
+      std::string o = ind;
+      ind += "  ";
+      emit_K_inline(mask);
+      const char* f[5] = {"qm", "qp", "q1", "q2", "mm"};
+      os << ind << "qx::propq<double> gq;\n";
+      for (int c = 0; c < 5; ++c) os << ind << "gq." << f[c] << " = " << gqref(kv.second, c) << ";\n";
+      prop_grad_to_momenta(side, mask);
+      ind = o;
+      os << ind << "}\n";
+    }
+  }
+
   // Emit the adjoint contribution of consumer c (of current x) into w<x>.
   void rev(int c, int x) {
     const Node& n = d.nodes[c];
@@ -676,6 +713,9 @@ struct Emitter {
     std::string outer = ind;
     ind += "  ";
     const bool leaf = leafJ.count(c) > 0;
+    // adjoint of c: its own accumulator, or (factored block, column leaf)
+    // the seed shared by the leaves of its configurations
+    const std::string wc = (leaf && factored) ? "W" + std::to_string(memJ.at(c)) : "w" + std::to_string(c);
     if (n.kind == Kind::S1) {
       emit_K_inline(n.mask);
       int pe = n.side == 0 ? pr.i_ein : pr.i_eout;
@@ -692,19 +732,33 @@ struct Emitter {
         os << ind << "const qx::sp4<double> f" << c << " = qx::v" << side << "<double>(" << X << ", " << E << ");\n";
       else
         os << ind << "const qx::sp4<double> f" << c << " = qx::s" << side << "<double>(" << X << ", q);\n";
-      os << ind << "qx::sp4<double> w" << c << " = qx::zero4<double>();\n";
-      st.flops_per_point += n.kind == Kind::V ? 40 : 56;
-      for (int c2 : cons[c]) rev(c2, c);
+      if (factored && memB.count(c)) {
+        // row leaf of a factored block: its adjoint is the row seed of its
+        // configurations, and it joins their row sum
+        os << ind << "const qx::sp4<double> w" << c << " = T" << memB.at(c) << ";\n";
+        os << ind << "qx::add_to(SB" << memB.at(c) << ", f" << c << ");\n";
+        st.flops_per_point += n.kind == Kind::V ? 40 + 8 : 56 + 8;
+      } else {
+        os << ind << "qx::sp4<double> w" << c << " = qx::zero4<double>();\n";
+        st.flops_per_point += n.kind == Kind::V ? 40 : 56;
+        for (int c2 : cons[c]) rev(c2, c);
+      }
     }
     if (n.kind == Kind::V) {
-      os << ind << "qx::add_to(w" << x << ", qx::v" << other << "<double>(w" << c << ", " << E << "));\n";
-      os << ind << "qx::v" << side << "_ge<double>(w" << c << ", " << X << ", ge" << producer(n.in[0]) << ");\n";
+      os << ind << "qx::add_to(w" << x << ", qx::v" << other << "<double>(" << wc << ", " << E << "));\n";
+      os << ind << "qx::v" << side << "_ge<double>(" << wc << ", " << X << ", ge" << producer(n.in[0]) << ");\n";
       st.flops_per_point += 40 + 48;
     } else {
-      os << ind << "qx::add_to(w" << x << ", qx::s" << other << "<double>(w" << c << ", q));\n";
+      os << ind << "qx::add_to(w" << x << ", qx::s" << other << "<double>(" << wc << ", q));\n";
       os << ind << "qx::propq<double> gq = {0.0, 0.0, 0.0, 0.0, 0.0};\n";
-      os << ind << "qx::s" << side << "_gq<double>(w" << c << ", " << X << ", gq);\n";
-      prop_grad_to_momenta(n.side, n.mask);
+      os << ind << "qx::s" << side << "_gq<double>(" << wc << ", " << X << ", gq);\n";
+      if (gq_in_lds) {
+        const int k = gq_index(n.side, n.mask);
+        const char* f[5] = {"qm", "qp", "q1", "q2", "mm"};
+        for (int c = 0; c < 5; ++c) os << ind << gqref(k, c) << " += gq." << f[c] << ";\n";
+      } else {
+        prop_grad_to_momenta(n.side, n.mask);
+      }
       st.flops_per_point += 56 + 64 + 60;
     }
     ind = outer;
@@ -863,6 +917,62 @@ struct Emitter {
     close_block(outer);
   }
 
+  // Factored adjoint of a partition block.  For each configuration a the
+  // block's dots pair every row leaf B of a with every column leaf J of a
+  // (all orderings of the photons on either side), so the block's share of
+  // the amplitude is A_a = (sum_B B) . (sum_J J) and its adjoint needs only
+  // the sums: w_B = sum_{a: B in a} c_a SJ_a, w_J = sum_{a: J in a} c_a SB_a.
+  // No leaf or leaf adjoint is held across the other side's sweep; the
+  // sums are kept per membership pattern (the set of configurations a leaf
+  // belongs to, a bit mask over the block's accumulators).
+  bool factored = false;
+  std::map<int, uint32_t> memB, memJ;
+
+  bool factor_block(const std::vector<int>& dk) {
+    memB.clear();
+    memJ.clear();
+    std::map<int, std::set<std::pair<int, int>>> pairs;
+    for (int k : dk) {
+      const Node& dn = d.nodes[k];
+      if (dn.kind != Kind::Dot) return false;
+      auto ops = dot_ops(dn);
+      int J = producer(ops.first), B = producer(ops.second);
+      int a = acc_of_sum.at(d.nodes[dn.out[0]].out[0]);
+      if (a >= 32 || !pairs[a].insert({B, J}).second) return false;
+      memB[B] |= 1u << a;
+      memJ[J] |= 1u << a;
+    }
+    for (auto& kv : pairs) {
+      std::set<int> Bs, Js;
+      for (auto& bj : kv.second) {
+        Bs.insert(bj.first);
+        Js.insert(bj.second);
+      }
+      if (kv.second.size() != Bs.size() * Js.size()) return false;
+    }
+    for (auto& kv : memB) {
+      const Node& b = d.nodes[kv.first];
+      if (b.kind != Kind::S1 && b.kind != Kind::V) return false;
+      for (int c2 : cons[kv.first])
+        if (d.nodes[c2].kind != Kind::Dot) return false;
+    }
+    return true;
+  }
+
+  // sum over the configurations a in `pat` of c_a times the patterns' sums
+  // S<q> of every pattern q containing a
+  void emit_seed(const std::string& out, uint32_t pat, const std::string& S, const std::set<uint32_t>& pats) {
+    os << ind << "qx::sp4<double> " << out << " = qx::zero4<double>();\n";
+    for (int a = 0; a < 32; ++a) {
+      if (!((pat >> a) & 1)) continue;
+      for (uint32_t q : pats)
+        if ((q >> a) & 1) {
+          os << ind << "qx::axpy<double>(" << out << ", c" << a << ", " << S << q << ");\n";
+          st.flops_per_point += 32;
+        }
+    }
+  }
+
   void grad_block(uint32_t key, const std::vector<int>& dk) {
     collect_block(dk);
     os << ind << "// adjoint: photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << "\n";
@@ -877,13 +987,45 @@ struct Emitter {
     }
     leafJ.clear();
     for (int k : dk) leafJ.insert(producer(dot_ops(d.nodes[k]).first));
-    for (int J : leafJ) {
-      emit(J);
-      os << ind << "qx::sp4<double> w" << J << " = qx::zero4<double>();\n";
+    factored = factor_block(dk);
+    std::set<uint32_t> patB, patJ;
+    if (factored) {
+      for (auto& kv : memB) patB.insert(kv.second);
+      for (auto& kv : memJ) patJ.insert(kv.second);
+      // column sums per pattern, from a forward walk of the column trie in a
+      // scope of its own (its currents die with it; the column sweep below
+      // recomputes them)
+      for (uint32_t q : patJ) os << ind << "qx::sp4<double> SJ" << q << " = qx::zero4<double>();\n";
+      os << ind << "{\n";
+      std::string o = ind;
+      ind += "  ";
+      std::vector<char> done0 = done;
+      std::set<uint32_t> kdone0 = kdone;
+      std::set<std::pair<int, uint32_t>> qdone0 = qdone;
+      for (int J : leafJ) {
+        emit(J);
+        os << ind << "qx::add_to(SJ" << memJ.at(J) << ", " << name(J) << ");\n";
+        st.flops_per_point += 8;
+      }
+      done = done0;
+      kdone = kdone0;
+      qdone = qdone0;
+      ind = o;
+      os << ind << "}\n";
+      // row seeds, and the row sums the row sweep accumulates
+      for (uint32_t q : patB) emit_seed("T" + std::to_string(q), q, "SJ", patJ);
+      for (uint32_t q : patB) os << ind << "qx::sp4<double> SB" << q << " = qx::zero4<double>();\n";
+    } else {
+      for (int J : leafJ) {
+        emit(J);
+        os << ind << "qx::sp4<double> w" << J << " = qx::zero4<double>();\n";
+      }
     }
     // e-_out side trie (dots at its leaves), then e-_in side trie
     for (int pass = 0; pass < 2; ++pass) {
       int root_particle = pass == 0 ? pr.i_eout : pr.i_ein;
+      if (pass == 1 && factored)
+        for (uint32_t q : patJ) emit_seed("W" + std::to_string(q), q, "SB", patB);
       for (int r : blk) {
         const Node& n = d.nodes[r];
         if (n.kind != Kind::U || n.particle != root_particle) continue;
@@ -1251,6 +1393,7 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     Emitter e(d, v);
     e.mom_src = 0;       // momenta reloaded per block from the workspace
     e.gm_in_lds = true;  // gradient accumulators in per-lane LDS slots
+    e.gq_in_lds = !d.distributed;  // propagator gradients per propagator, flushed once
     std::vector<int> sums = e.sum_nodes();
     for (size_t a = 0; a < sums.size(); ++a) e.acc_of_sum[sums[a]] = (int)a;
     std::ostringstream& os = e.os;
@@ -1258,12 +1401,16 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
        << "(const double* __restrict__ mom, const double* __restrict__ amp, const double* __restrict__ im2, "
           "long long N, double* __restrict__ gm)\n{\n";
     os << "  __shared__ double qx_gm[" << 4 * pr.npart * v.block << "];\n";
+    const std::string gq_mark = "  //@GQ@\n";
+    os << gq_mark;
     os << "  const long long gid = (long long)blockIdx.x * " << v.block << " + threadIdx.x;\n";
     os << "  const long long pt = gid >> " << LB << ";\n";
     os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
     os << "  const long long ptc = pt < N ? pt : N - 1;\n";
     for (int p = 2; p < pr.npart; ++p)
       for (int mu = 0; mu < 4; ++mu) os << "  " << e.gmref(p, mu) << " = 0.0;\n";
+    const std::string gq_zero_mark = "  //@GQZERO@\n";
+    os << gq_zero_mark;
     os << "  const double iM2 = im2[ptc];\n";
     os << "  const unsigned hrt = " << Emitter::deposit("sub", v.lane_mask) << ";\n";
     os << "  #pragma unroll 1\n  for (unsigned lp = 0; lp < " << (1u << nloop) << "u; ++lp) {\n";
@@ -1281,6 +1428,15 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
       e.grad_block(key, part[key]);
     e.ind = "  ";
     os << "  }\n";
+    if (!e.gq_slot.empty()) {
+      // propagator gradients of every iteration -> momentum gradients
+      os << "  {\n";
+      e.ind = "    ";
+      e.load_momenta("mom", "N", "ptc");
+      e.flush_gq();
+      e.ind = "  ";
+      os << "  }\n";
+    }
     for (int p = 2; p < pr.npart; ++p)
       for (int mu = 0; mu < 4; ++mu) {
         os << "  double gm" << p << "_" << mu << " = " << e.gmref(p, mu) << ";\n";
@@ -1294,6 +1450,17 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     os << "  }\n}\n";
     tot.flops_per_point += e.st.flops_per_point * (double)G * (double)(1 << nloop);
     std::string ks = os.str();
+    {
+      const int ns = (int)e.gq_slot.size();
+      std::string decl, zero;
+      if (ns > 0) {
+        decl = "  __shared__ double qx_gq[" + std::to_string(5 * ns * v.block) + "];\n";
+        for (int k = 0; k < ns; ++k)
+          for (int c = 0; c < 5; ++c) zero += "  " + e.gqref(k, c) + " = 0.0;\n";
+      }
+      ks.replace(ks.find(gq_mark), gq_mark.size(), decl);
+      ks.replace(ks.find(gq_zero_mark), gq_zero_mark.size(), zero);
+    }
     all << ks;
     ++t;
   }

@@ -217,10 +217,11 @@ static qed_status get_code_object(const std::string& tag, const std::string& src
       return QED_OK;
     }
   }
-  if (getenv("QEDX_NO_COMPILE"))
-    return fail(QED_ERR_COMPILE, "code object " + path + " missing or corrupt and QEDX_NO_COMPILE is set");
   std::string srcp = base + ".hip";
   if (!write_file(srcp, src)) return fail(QED_ERR_COMPILE, "cannot write " + srcp);
+  if (getenv("QEDX_NO_COMPILE"))
+    return fail(QED_ERR_COMPILE, "code object " + path + " missing or corrupt and QEDX_NO_COMPILE is set (source in " +
+                                     srcp + ")");
   std::string tmpo = base + ".o.tmp" + std::to_string(getpid()) + "_" +
                      std::to_string(std::hash<std::thread::id>()(std::this_thread::get_id()));
   std::string tmpl = log + ".tmp" + std::to_string(getpid()) + "_" +
@@ -835,6 +836,16 @@ extern "C" qed_status qed_graph_metrics(int n, int n_in, uint32_t enum_mask, int
   Dag d = tool_graph(n, n_in, enum_mask, split, reduced);
   if (c_dag) *c_dag = compute_effort(d, fp32 != 0);
   if (d_dag) *d_dag = data_transfer(d, fp32 != 0);
+  return QED_OK;
+}
+
+extern "C" qed_status qed_graph_adjoint_metrics(int n, uint32_t enum_mask, int split, int reduced, double* c_fwd,
+                                                double* c_adj) {
+  qed_status s = check_tool_args(n, 1, enum_mask, split);
+  if (s) return s;
+  Dag d = tool_graph(n, 1, enum_mask, split, reduced);
+  if (c_fwd) *c_fwd = compute_effort(d, false);
+  if (c_adj) *c_adj = adjoint_effort(d);
   return QED_OK;
 }
 

@@ -275,6 +275,14 @@ def graph_metrics(n: int, n_in: int = 1, enum_mask: int = 0, split: Optional[int
     return c.value, d.value
 
 
+def graph_adjoint_metrics(n: int, enum_mask: int = 0, split: Optional[int] = None, reduced: bool = True):
+    """(forward C(DAG), reverse-mode cost) in FLOPs per point for e- gamma -> e- n gamma."""
+    split = split if split is not None else (n + 1) // 2
+    c, a = ctypes.c_double(), ctypes.c_double()
+    check(lib().qed_graph_adjoint_metrics(n, enum_mask, split, int(reduced), ctypes.byref(c), ctypes.byref(a)))
+    return c.value, a.value
+
+
 def reduction_check(n: int, seed: int, n_in: int = 1, enum_mask: int = 0, split: Optional[int] = None):
     split = split if split is not None else (n + n_in) // 2
     size = 1 << 22

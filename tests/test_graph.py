@@ -239,3 +239,24 @@ def test_crossed_graph_equals_oracle(n_in, n_out, reduced):
     all_mask = (1 << npart) - 1
     got_s = Q.graph_interpret(n_out, flat, None, n_in=n_in, enum_mask=all_mask, reduced=reduced)
     assert np.max(np.abs(got_s / tot - 1)) < 1e-11
+
+
+def test_adjoint_cost_model():
+    """The gradient's algorithmic FLOPs (forward C(DAG) plus the reverse-mode
+    cost of the same graph): the forward part equals C(DAG); by node, the
+    adjoint of a vertex costs 2.5x its forward (3.5x for the y polarisation),
+    of a propagator 2.2x, and the dots of one amplitude in one photon
+    partition take their adjoint from the two leaf sums, so the ratio of the
+    total to the forward lies between 2 and 4.5 (lower for larger n, where
+    dots dominate the forward count); node reduction lowers both."""
+    for n in (1, 2, 3, 4):
+        m = (1 << (n + 3)) - 1
+        f, a = Q.graph_adjoint_metrics(n, enum_mask=m)
+        assert f == Q.graph_metrics(n, enum_mask=m, split=(n + 1) // 2)[0]
+        assert 2.0 < (f + a) / f < 4.5, (n, f, a)
+        fu, au = Q.graph_adjoint_metrics(n, enum_mask=0, reduced=False)
+        fr, ar = Q.graph_adjoint_metrics(n, enum_mask=0, reduced=True)
+        assert fr <= fu and (n == 1 or ar < au)
+    from paper_2511_19456_amd._lib import QedError
+    with pytest.raises(QedError):
+        Q.graph_adjoint_metrics(0)

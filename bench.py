@@ -316,6 +316,28 @@ def extra_legs(torch, inputs, QedProcess, dev, a, want, ref_n3, mom_n3):
             return r
         return run
     _leg(legs, "n3_sum_fp64_distributive_2p20", want, distributive(3, "sum", 10.0, 2))
+
+    def mfma_join():
+        """The same distributive n = 3 helicity-sum graph with its joins (4 x 4
+        complex dot blocks per photon partition) on the FP64 matrix cores,
+        against its vector joins, on the headline points."""
+        from paper_2511_19456_amd.qedx import make_variant
+        N = ref_n3.numel()
+        vec = QedProcess(3, "sum", "fp64", make_variant(rewrite=1))
+        mat = QedProcess(3, "sum", "fp64", make_variant(rewrite=1, order=128))
+        o0 = torch.empty(N, dtype=torch.float64, device=dev)
+        o1 = torch.empty(N, dtype=torch.float64, device=dev)
+        ms0 = time_launches(lambda: vec.eval(mom_n3, out=o0), steps, 2)
+        ms1 = time_launches(lambda: mat.eval(mom_n3, out=o1), steps, 2)
+        fl = alg_flops(3, "sum", rewrite=1)
+        r = rate(ms1, N, fl, FP64_VECTOR_PEAK_TFLOPS)
+        i0, i1 = vec.info(), mat.info()
+        r.update({"ms_vector_join": ms0, "speedup_vs_vector_join": ms0 / ms1,
+                  "rel_diff_vs_vector_join": rel_err_stats(o1, o0), "kernel": i1["kernel_name"],
+                  "vgpr_agpr_scratch": [i1["vgpr"], i1["agpr"], i1["scratch_bytes"]],
+                  "vector_vgpr_agpr_scratch": [i0["vgpr"], i0["agpr"], i0["scratch_bytes"]]})
+        return r
+    _leg(legs, "n3_sum_fp64_distributive_mfma_join_2p20", want, mfma_join)
     _leg(legs, "n5_per_point_fp64_distributive_2p20", want, distributive(5, "per_point", 20.0, 3))
     _leg(legs, "n6_per_point_fp64_distributive_2p20", want, distributive(6, "per_point", 25.0, 3))
 

@@ -129,6 +129,8 @@ DEFAULT_KERNELS = [
     (4, 0, 0, dict(rewrite=1)), (4, 1, 0, dict(rewrite=1)), (5, 1, 0, dict(rewrite=1)), (6, 1, 0, dict(rewrite=1)),
     (1, 1, 0, dict(rewrite=1)), (2, 1, 0, dict(rewrite=1)), (3, 1, 0, dict(rewrite=1)),
     (3, 0, 1, dict(rewrite=1)), (5, 1, 1, dict(rewrite=1)),
+    # the join of the distributive n = 3 helicity sum on the FP64 matrix cores (experiment)
+    (3, 0, 0, dict(rewrite=1, order=128)),
     # kernel shapes the parity tests exercise
     (3, 0, 0, dict(lane_bits=7)), (3, 0, 0, dict(lane_bits=5, order=4)), (3, 0, 0, dict(lane_bits=63, order=4)),
     (3, 1, 0, dict(order=4)), (3, 0, 0, dict(lane_bits=5, order=16)), (3, 0, 0, dict(lane_bits=5, loop_bits=2, order=32)),

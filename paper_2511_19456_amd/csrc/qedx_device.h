@@ -189,6 +189,37 @@ template <class T> QEDX_HD void comp_acc(cx<T>& s, cx<T>& c, const cx<T>& x) {
 }
 
 // ---------------------------------------------------------------------------
+// Join on the FP64 matrix cores (experiment): the 4 x 4 complex dot matrices
+// D[i][j] = sum_k R_i[k] J_j[k] of the 64 lanes of a wave, two lanes per
+// pair of v_mfma_f64_4x4x4 (4 blocks of 4 x 4 x 4).  stg holds, per lane
+// (stride doubles apart), R_re[i][k] at 4i+k, R_im at 16+4i+k, J_re[j][k] at
+// 32+4j+k, J_im at 48+4j+k.  Block b of pair t: lane 2t + (b >> 1), real
+// part for even b (R_re J_re^T - R_im J_im^T), imaginary for odd b
+// (R_re J_im^T + R_im J_re^T).  Operand lanes: A[b][i][k] at 16k + 4b + i,
+// B[b][k][j] at 16k + 4b + j; result C[b][i][j] at 16i + 4b + j.  mj[t] +=
+// the result of lane src (the caller's permutation into its accumulator
+// layout).  Device only; all 64 lanes of the wave must be active.
+// ---------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ inline void mfma_join4(const double* stg, int stride, int src, double (&mj)[32]) {
+  const int l = (int)(threadIdx.x & 63);
+  const int k = l >> 4, b = (l >> 2) & 3, r = l & 3;
+  const bool im = (b & 1) != 0;
+#pragma unroll
+  for (int t = 0; t < 32; ++t) {
+    const double* q = stg + (2 * t + (b >> 1)) * stride;
+    const double a1 = q[4 * r + k];
+    const double b1 = q[(im ? 48 : 32) + 4 * r + k];
+    const double a2 = im ? q[16 + 4 * r + k] : -q[16 + 4 * r + k];
+    const double b2 = q[(im ? 32 : 48) + 4 * r + k];
+    double c = __builtin_amdgcn_mfma_f64_4x4x4f64(a1, b1, 0.0, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_4x4x4f64(a2, b2, c, 0, 0, 0);
+    mj[t] += __shfl(c, src);
+  }
+}
+#endif
+
+// ---------------------------------------------------------------------------
 // U: external states (base_state) from momenta, double precision.
 // u(p, s): psi_L = ((E+m) - p.sigma) chi / sqrt(2(E+m)),
 //          psi_R = ((E+m) + p.sigma) chi / sqrt(2(E+m)),  chi_0 = (1,0), chi_1 = (0,1).

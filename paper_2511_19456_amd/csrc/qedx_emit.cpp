@@ -9,6 +9,7 @@
 #include "qedx_emit.hpp"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <map>
 #include <set>
@@ -565,6 +566,10 @@ struct Emitter {
     std::map<uint32_t, std::vector<int>> part;
     std::vector<uint32_t> order;
     partitions(part, order);
+    if (mfma_join()) {
+      mfma_body(part, order, (int)sums.size());
+      return;
+    }
     if (slot) {
       slot_loop(part);
     } else {
@@ -589,6 +594,113 @@ struct Emitter {
       st.flops_per_point += 4;
     }
   }
+
+  // ---------------------------------------------------------------------
+  // Join on the FP64 matrix cores (order flag 128; a measured experiment,
+  // not a default).  Graphs whose every photon partition pairs 4 row
+  // currents with 4 column currents, each pair the dot of a different one
+  // of 16 amplitudes (the distributive helicity-sum graph with 4 photons
+  // and the spins on lanes): per partition, each lane stores its row and
+  // column currents in the wave's LDS staging area, and the 4 x 4 complex
+  // dot matrices of two lanes at a time are computed by two
+  // v_mfma_f64_4x4x4 (real part R_re J_re^T - R_im J_im^T and imaginary
+  // part R_re J_im^T + R_im J_re^T, K = 4 spinor components).  Every
+  // partition maps the 16 amplitudes to the 4 x 4 positions differently; a
+  // lane permutation (__shfl) brings them to the first partition's layout
+  // before they are accumulated.  The amplitudes are then gathered back to
+  // their lanes through LDS for |A|^2.
+  // ---------------------------------------------------------------------
+  bool mfma_join() const { return (v.order & 128) != 0; }
+  std::string mj_tab;  // kernel-name prefix of the per-partition permutation tables
+
+  void mfma_body(std::map<uint32_t, std::vector<int>>& part, const std::vector<uint32_t>& order, int nsum) {
+    if (v.prec != PREC_F64 || nsum != 16 || slot || stage())
+      throw std::invalid_argument("the matrix-core join takes FP64 graphs with 16 amplitudes per lane");
+    // per partition: row and column currents (index = position in the 4 x 4
+    // block) and the amplitude of every position
+    std::vector<std::array<int, 16>> pos_amp;
+    std::vector<std::vector<int>> rows, cols;
+    for (uint32_t key : order) {
+      std::vector<int> B, J;
+      std::array<int, 16> pa;
+      pa.fill(-1);
+      for (int k : part[key]) {
+        const Node& dn = d.nodes[k];
+        if (dn.kind != Kind::Dot) throw std::invalid_argument("matrix-core join: split joins only");
+        auto ops = dot_ops(dn);
+        int j = producer(ops.first), b = producer(ops.second);
+        if (std::find(B.begin(), B.end(), b) == B.end()) B.push_back(b);
+        if (std::find(J.begin(), J.end(), j) == J.end()) J.push_back(j);
+        int r = (int)(std::find(B.begin(), B.end(), b) - B.begin());
+        int c = (int)(std::find(J.begin(), J.end(), j) - J.begin());
+        if (r > 3 || c > 3) throw std::invalid_argument("matrix-core join: a partition with more than 4 x 4 currents");
+        int a = acc_of_sum.at(d.nodes[dn.out[0]].out[0]);
+        if (pa[4 * r + c] >= 0) throw std::invalid_argument("matrix-core join: repeated dot");
+        pa[4 * r + c] = a;
+      }
+      for (int x : pa)
+        if (x < 0) throw std::invalid_argument("matrix-core join: incomplete 4 x 4 block");
+      rows.push_back(B);
+      cols.push_back(J);
+      pos_amp.push_back(pa);
+    }
+    // position of every amplitude in the first partition (the accumulator layout)
+    std::array<int, 16> pos0;
+    for (int q = 0; q < 16; ++q) pos0[pos_amp[0][q]] = q;
+    os << ind << "double mj[32];\n" << ind << "#pragma unroll\n" << ind << "for (int t = 0; t < 32; ++t) mj[t] = 0.0;\n";
+    os << ind << "double* const mj_stg = qx_mj + (threadIdx.x >> 6) * " << 64 * kMjStride << ";\n";
+    os << ind << "const int mj_lane = (int)(threadIdx.x & 63);\n";
+    for (size_t p = 0; p < order.size(); ++p) {
+      fence(1);
+      os << ind << "// photons " << order[p] << " | " << (((1u << pr.P) - 1) & ~order[p])
+         << " on the e-_in | e-_out side: 4 x 4 dots on the matrix cores\n";
+      for (int b : rows[p]) emit(b);
+      for (int j : cols[p]) emit(j);
+      os << ind << "{\n";
+      std::string o = ind;
+      ind += "  ";
+      os << ind << "double* const st_ = mj_stg + mj_lane * " << kMjStride << ";\n";
+      for (int r = 0; r < 4; ++r)
+        for (int k = 0; k < 4; ++k) {
+          os << ind << "st_[" << 4 * r + k << "] = " << name(rows[p][r]) << ".c[" << k << "].r; st_[" << 16 + 4 * r + k
+             << "] = " << name(rows[p][r]) << ".c[" << k << "].i;\n";
+          os << ind << "st_[" << 32 + 4 * r + k << "] = " << name(cols[p][r]) << ".c[" << k << "].r; st_["
+             << 48 + 4 * r + k << "] = " << name(cols[p][r]) << ".c[" << k << "].i;\n";
+        }
+      // source lane (within the lane's block) of the accumulator position
+      // (i, j) = ((lane >> 4), lane & 3): where this partition put that amplitude
+      os << ind << "const int src_ = " << mj_tab << "[" << p << " * 16 + ((mj_lane >> 4) << 2) + (mj_lane & 3)] + (mj_lane & 12);\n";
+      os << ind << "qx::mfma_join4(mj_stg, " << kMjStride << ", src_, mj);\n";
+      ind = o;
+      os << ind << "}\n";
+      st.flops_per_point += 16 * 32;
+      st.n_dot += 16;
+      (void)pos0;
+    }
+    // amplitudes back to their lanes, then |A|^2
+    os << ind << "#pragma unroll\n" << ind << "for (int t = 0; t < 32; ++t) {\n";
+    os << ind << "  const int blk_ = (mj_lane >> 2) & 3;\n";
+    os << ind << "  mj_stg[(2 * t + (blk_ >> 1)) * " << kMjStride << " + (blk_ & 1) * 16 + (mj_lane >> 4) * 4 + (mj_lane & 3)] = mj[t];\n";
+    os << ind << "}\n";
+    os << ind << "#pragma unroll\n" << ind << "for (int q = 0; q < 32; ++q) { const double v_ = mj_stg[mj_lane * " << kMjStride
+       << " + q]; acc += v_ * v_; }\n";
+    st.flops_per_point += 16 * 4;
+    // permutation tables: entry (i0, j0) of partition p is 16 i_p + j_p
+    std::ostringstream tab;
+    tab << "__constant__ int " << mj_tab << "[" << 16 * order.size() << "] = {";
+    for (size_t p = 0; p < order.size(); ++p)
+      for (int q0 = 0; q0 < 16; ++q0) {
+        int a = pos_amp[0][q0];
+        int qp = -1;
+        for (int q = 0; q < 16; ++q)
+          if (pos_amp[p][q] == a) qp = q;
+        tab << (p || q0 ? ", " : "") << 16 * (qp >> 2) + (qp & 3);
+      }
+    tab << "};\n";
+    mj_tables = tab.str();
+  }
+  std::string mj_tables;
+  static constexpr int kMjStride = 65;  // doubles per lane in the staging area (padded against bank conflicts)
 
   // ---------------------------------------------------------------------
   // Adjoint pass.  Per partition block: the e-_in-side leaves are recomputed
@@ -1152,6 +1264,12 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     e.slot_tab = kname + "_slots";
     e.emit_slot_table();
   }
+  e.mj_tab = kname + "_mjperm";
+  const std::string mj_mark = "//@MJTAB@\n";
+  if (e.mfma_join()) {
+    if (v.block != 256) throw std::invalid_argument("the matrix-core join takes 256-lane workgroups");
+    os << mj_mark;
+  }
   os << "extern \"C\" __global__ void __launch_bounds__(" << v.block;
   if (v.min_waves > 0) os << ", " << v.min_waves;
   os << ")\n" << kname
@@ -1185,8 +1303,10 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
       decl = "  __shared__ " + e.T + " qx_lds[" + std::to_string(e.lds_slots * 8 * v.block) + "];\n";
     if (e.pol_lds)
       decl += "  __shared__ " + e.PT + " qx_pol[" + std::to_string(3 * d.proc.npart * v.block) + "];\n";
+    if (e.mfma_join()) decl += "  __shared__ double qx_mj[" + std::to_string(4 * 64 * Emitter::kMjStride) + "];\n";
     size_t at = src.find(lds_mark);
     src.replace(at, lds_mark.size(), decl);
+    if (e.mfma_join()) src.replace(src.find(mj_mark), mj_mark.size(), e.mj_tables);
   }
   if (v.fixup) {
     // FP64 pass over the points the FP32C kernel could not resolve

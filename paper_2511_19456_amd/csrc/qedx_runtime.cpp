@@ -382,6 +382,7 @@ static std::string eval_kernel_name(int n, int nin, qed_hel_mode mode, qed_preci
                   (mode == QED_HEL_SUM ? "_sum" : "_pp") + (prec == QED_FP64 ? "_fp64" : "_fp32c");
   if (v.rewrite) k += "_d" + std::to_string(v.rewrite);
   if (v.partial) k += "_k" + std::to_string(v.partial_steps);
+  if (v.order & 128) k += "_mfma";
   return k;
 }
 

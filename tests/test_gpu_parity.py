@@ -298,6 +298,27 @@ def test_distributive_rewrite_fp64(n, mode, sqrt_s, lanes, N):
         check_fp64(got, ref, kap, f"distributive n={n}")
 
 
+@pytest.mark.parametrize("N", [517, 64 * 4 * 3 + 5, 1])
+def test_distributive_join_on_matrix_cores(N):
+    """The n = 3 helicity-sum distributive kernel with its joins on the FP64
+    matrix cores (4 x 4 complex dot blocks by v_mfma_f64_4x4x4, lanes
+    permuted per partition; the join task of Sec. II-B): against the oracle
+    at 1e-10 and against the same graph's vector joins, on a ragged point
+    count, several full waves and a single point."""
+    from paper_2511_19456_amd.qedx import make_variant
+    n, sqrt_s = 3, 10.0
+    u, _ = inputs.rambo_inputs(33, n, N)
+    ref_mom = O.momenta_soa_from_uniforms(u, sqrt_s, n)
+    p = _proc(n, "sum", "fp64", make_variant(rewrite=1, order=128))
+    assert p.info()["kernel_name"].endswith("_mfma")
+    m = torch.as_tensor(ref_mom.numpy(), device=DEV)
+    got = p.eval(m).cpu().numpy()
+    ref = O.m2(ref_mom, n, "sum").numpy()
+    assert _rel(got, ref).max() < 1e-10
+    vec = _proc(n, "sum", "fp64", make_variant(rewrite=1)).eval(m).cpu().numpy()
+    assert _rel(got, vec).max() < 1e-13
+
+
 @pytest.mark.parametrize("n,mode,sqrt_s", [(3, "sum", 10.0), (5, "per_point", 20.0)])
 def test_distributive_rewrite_fp32c(n, mode, sqrt_s):
     from paper_2511_19456_amd.qedx import make_variant

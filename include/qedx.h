@@ -85,7 +85,7 @@ typedef struct {
   uint32_t loop_bits;
   int32_t block;
   int32_t split;
-  int32_t min_waves;    /* minimum waves per SIMD the compiler must allow (0 = free) */
+  int32_t min_waves;    /* minimum waves per SIMD the compiler must allow (0 = library default) */
   int32_t order;        /* emission schedule flags (0 = library default) */
   int32_t use_defaults; /* nonzero: ignore the fields above and below */
   int32_t rewrite;      /* 0 = node reduction only (the paper's CDAG optimisation, App. C);

@@ -86,7 +86,11 @@ typedef struct {
   int32_t block;
   int32_t split;
   int32_t min_waves;    /* minimum waves per SIMD the compiler must allow (0 = library default) */
-  int32_t order;        /* emission schedule flags (0 = library default) */
+  int32_t order;        /* emission schedule flags (0 = library default).  Per-point FP64
+                           partition loops (8) may add the one-photon current cache: 256 =
+                           2 lanes per point, 512 = 4 lanes per point, 1024 = cache the
+                           e-_in side's currents only; qed_process_info reports the
+                           resulting lanes_per_point */
   int32_t use_defaults; /* nonzero: ignore the fields above and below */
   int32_t rewrite;      /* 0 = node reduction only (the paper's CDAG optimisation, App. C);
                            1 = node reduction followed by the distributive rewrite the paper
@@ -219,7 +223,9 @@ typedef struct {
   double* out;           /* device [N] */
 } qed_segment;
 
-/* tile_points = points per work tile, a multiple of 64 (0 = autotuned: a few
+/* tile_points = lanes per work tile, a multiple of 64: points per tile for
+ * processes with one lane per point, half or a quarter of it for processes
+ * whose body splits a point over 2 or 4 lanes (0 = autotuned: a few
  * grid sizes and tile lengths are timed on the given buffers, which are
  * overwritten, after a device synchronisation; the choice is cached by plan
  * signature).  The plan copies the segment table to the device, allocates a

@@ -134,13 +134,46 @@ struct Emitter {
   // read by slot inside it, instead of once per partition
   bool pol_lds = false;
   static constexpr int kTile = 4;
+  // One-photon current cache (order flag 256, per-point FP64 slot loops):
+  // the two lanes of a point first compute, for every photon, its
+  // polarisation vector and its one-photon currents on both sides,
+  // S(Q) eps-slash u and ubar eps-slash S(Q), into per-point LDS; the
+  // partition loop, split between the two lanes, reads them there instead of
+  // recomputing them in every partition (each photon's one-photon current
+  // is otherwise rebuilt once per partition that puts the photon first on a
+  // side).  BP = points per workgroup.
+  bool cur_cache = false;
+  int BP = 0, CL = 1;  // points per workgroup, lanes per point
+  bool k_lds = false;  // the signed photon momenta cached too (where LDS allows)
+  bool row_only = false;  // order flag 1024: only the e-_in side's currents cached
+  // a device-function body of the persistent batch kernel: the cache is the
+  // wave's own LDS region (BP = points per wave), tpt and sub are arguments,
+  // and the wave synchronises only itself
+  bool body_mode = false;
+  void wave_sync() {
+    os << ind << "__builtin_amdgcn_fence(__ATOMIC_RELEASE, \"wavefront\"); __builtin_amdgcn_wave_barrier(); "
+       << "__builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"wavefront\");\n";
+  }
+  std::string ix_tab;  // photon index of every slot: [iteration][P]
+  std::string cache_k(const std::string& ix, int mu) const {
+    return "qx_k[(4 * " + ix + " + " + std::to_string(mu) + ") * " + std::to_string(BP) + " + tpt]";
+  }
+  std::string cache_pol(const std::string& ix, int c) const {
+    return "qx_pol[(3 * " + ix + " + " + std::to_string(c) + ") * " + std::to_string(BP) + " + tpt]";
+  }
+  std::string cache_cur(int side, const std::string& ix, int w) const {
+    return "qx_cur[(" + std::to_string(side * pr.P * 8 + w) + " + 8 * " + ix + ") * " + std::to_string(BP) + " + tpt]";
+  }
 
   void emitK(uint32_t mask) {
     if (kdone.count(mask)) return;
     int lo = __builtin_ctz(mask);
     uint32_t rest = mask & (mask - 1);
     std::string km = "K" + std::to_string(mask);
-    if (rest == 0 && slot) {
+    if (rest == 0 && slot && k_lds) {
+      for (int mu = 0; mu < 4; ++mu)
+        os << ind << "const double " << km << "_" << mu << " = " << cache_k("ix" + std::to_string(lo), mu) << ";\n";
+    } else if (rest == 0 && slot) {
       for (int mu = 0; mu < 4; ++mu)
         os << ind << "const double " << km << "_" << mu << " = sg" << lo << " * k" << lo << "_" << mu << ";\n";
       st.flops_per_point += 4;
@@ -215,6 +248,16 @@ struct Emitter {
     int c = producer(i);
     if (done[c]) return;
     const Node& n = d.nodes[c];
+    if (cur_cache && n.kind == Kind::S1 && popc(n.mask) == 1 && (n.side == 0 || !row_only)) {
+      // a one-photon current: read from the per-point cache
+      const std::string ix = "ix" + std::to_string(__builtin_ctz(n.mask));
+      os << ind << "const qx::sp4<double> n" << c << " = {{";
+      for (int k = 0; k < 4; ++k)
+        os << (k ? ", " : "") << "{" << cache_cur(n.side, ix, 2 * k) << ", " << cache_cur(n.side, ix, 2 * k + 1) << "}";
+      os << "}};\n";
+      done[c] = 1;
+      return;
+    }
     for (int p : n.in) emit(p);
     std::string nm = "n" + std::to_string(c);
     switch (n.kind) {
@@ -233,8 +276,10 @@ struct Emitter {
           std::string sp = "sp" + std::to_string(slot_of(p));
           os << ind << "const qx::pol3<" << TU << "> " << nu << " = {";
           for (int c = 0; c < 3; ++c)
-            os << (c ? ", " : "") << (PT != TU ? "(" + TU + ")" : std::string()) << "qx_pol[(3 * " << sp << " + " << c
-               << ") * " << v.block << " + threadIdx.x]";
+            os << (c ? ", " : "") << (PT != TU ? "(" + TU + ")" : std::string())
+               << (cur_cache ? cache_pol("ix" + std::to_string(slot_of(p)), c)
+                             : "qx_pol[(3 * " + sp + " + " + std::to_string(c) + ") * " + std::to_string(v.block) +
+                                   " + threadIdx.x]");
           os << "};\n";
           if (d1) os << ind << "const qx::pol3<float> " << nm << " = qx::to_f(" << nu << ");\n";
         } else {
@@ -510,6 +555,11 @@ struct Emitter {
     os << "__constant__ int " << slot_tab << "[" << tab.size() << "] = {";
     for (size_t i = 0; i < tab.size(); ++i) os << (i ? ", " : "") << tab[i];
     os << "};\n";
+    if (cur_cache) {
+      os << "__constant__ int " << ix_tab << "[" << tab.size() << "] = {";
+      for (size_t i = 0; i < tab.size(); ++i) os << (i ? ", " : "") << slot_of(tab[i]);
+      os << "};\n";
+    }
   }
 
   void slot_loop(std::map<uint32_t, std::vector<int>>& part) {
@@ -520,7 +570,7 @@ struct Emitter {
     for (int p : {pr.i_ein, pr.i_eout})
       for (int mu = 0; mu < 4; ++mu)
         os << ind << "const double m" << p << "_" << mu << " = mom[" << (4 * p + mu) << " * N + ptc];\n";
-    if (pol_lds)
+    if (pol_lds && !cur_cache)
       for (int a = 0; a < P; ++a) {
         int pp = pr.photon_particle[a];
         os << ind << "{ const qx::pol3<" << PT << "> e_ = qx::pol<" << PT << ">(mom[" << (4 * pp + 1) << " * N + ptc], mom["
@@ -529,15 +579,95 @@ struct Emitter {
           os << " qx_pol[" << (3 * pp + c) * v.block << " + threadIdx.x] = e_.e" << (c + 1) << ";";
         os << " }\n";
       }
-    os << ind << "#pragma unroll 1\n" << ind << "for (int it = 0; it < " << nit << "; ++it) {\n";
+    double pre = 0.0;  // FLOPs per lane before the loop
+    if (cur_cache) {
+      // photons sub, sub + 2, ... of the point: polarisation vector and the
+      // two one-photon currents into the per-point cache (photon index a is
+      // particle a + 1 for the n_in incoming photons, a + 2 after e-_out)
+      const int ein = pr.i_ein, eout = pr.i_eout, nin = eout - 1;
+      auto mref = [&](int p) {
+        std::string m = "m" + std::to_string(p) + "_";
+        return m + "0, " + m + "1, " + m + "2, " + m + "3";
+      };
+      if (body_mode)
+        wave_sync();  // the previous tile's reads of the region come first
+      else
+        os << ind << "const int tpt = (int)(threadIdx.x >> " << __builtin_ctz(CL) << ");\n";
+      os << ind << "const int q_ = (int)(sub & " << CL - 1 << "u);\n";
+      os << ind << "{\n";
+      os << ind << "  const qx::sp4<double> ue_ = qx::u_in<double>(" << mref(ein) << ", (int)((hc >> " << ein
+         << ") & 1u), 1.0);\n";
+      if (!row_only)
+        os << ind << "  const qx::sp4<double> ub_ = qx::ubar_out<double>(" << mref(eout) << ", (int)((hc >> " << eout
+           << ") & 1u), 1.0);\n";
+      os << ind << "  #pragma unroll\n" << ind << "  for (int j = 0; j < " << (P + CL - 1) / CL << "; ++j) {\n";
+      os << ind << "    const int a = " << CL << " * j + q_;\n";
+      os << ind << "    if (a < " << P << ") {\n";
+      os << ind << "      const int pp = a + (a < " << nin << " ? 1 : 2);\n";
+      os << ind << "      const double s_ = a < " << nin << " ? 1.0 : -1.0;\n";
+      os << ind << "      double k_[4];\n";
+      os << ind << "      for (int mu = 0; mu < 4; ++mu) k_[mu] = mom[(4 * pp + mu) * N + ptc];\n";
+      os << ind << "      const qx::pol3<double> e_ = qx::pol<double>(k_[1], k_[2], k_[3], (int)((hc >> pp) & 1u));\n";
+      for (int c = 0; c < 3; ++c) os << ind << "      " << cache_pol("a", c) << " = e_.e" << (c + 1) << ";\n";
+      if (k_lds)
+        for (int mu = 0; mu < 4; ++mu) os << ind << "      " << cache_k("a", mu) << " = s_ * k_[" << mu << "];\n";
+      os << ind << "      const qx::sp4<double> r_ = qx::sL<double>(qx::vL<double>(ue_, e_), qx::prop_from<double>("
+         << mref(ein) << ", s_ * k_[0], s_ * k_[1], s_ * k_[2], s_ * k_[3], 1.0, 1.0));\n";
+      if (!row_only)
+        os << ind << "      const qx::sp4<double> c_ = qx::sR<double>(qx::vR<double>(ub_, e_), qx::prop_from<double>("
+           << mref(eout) << ", s_ * k_[0], s_ * k_[1], s_ * k_[2], s_ * k_[3], -1.0, 1.0));\n";
+      for (int side = 0; side < (row_only ? 1 : 2); ++side)
+        for (int k = 0; k < 4; ++k)
+          os << ind << "      " << cache_cur(side, "a", 2 * k) << " = " << (side ? "c_" : "r_") << ".c[" << k << "].r; "
+             << cache_cur(side, "a", 2 * k + 1) << " = " << (side ? "c_" : "r_") << ".c[" << k << "].i;\n";
+      os << ind << "    }\n" << ind << "  }\n" << ind << "}\n";
+      if (body_mode)
+        wave_sync();
+      else
+        os << ind << "__syncthreads();\n";
+      pre = (row_only ? 16 : 2 * 16) + (P + CL - 1) / CL * (16 + 4 + (row_only ? 1 : 2) * (40 + 28 + 56));
+    }
     std::string outer = ind;
-    ind += "  ";
-    for (int a = 0; a < P; ++a) {
-      os << ind << "const int sp" << a << " = " << slot_tab << "[it * " << P << " + " << a << "];\n";
-      os << ind << "const double sg" << a << " = sp" << a << " < " << pr.i_eout << " ? 1.0 : -1.0;\n";
-      os << ind << "const int hb" << a << " = (int)((hc >> sp" << a << ") & 1u);\n";
-      for (int mu = 0; mu < 4; ++mu)
-        os << ind << "const double k" << a << "_" << mu << " = mom[(4 * sp" << a << " + " << mu << ") * N + ptc];\n";
+    if (!cur_cache) {
+      os << ind << "#pragma unroll 1\n" << ind << "for (int it = 0; it < " << nit << "; ++it) {\n";
+      ind += "  ";
+      for (int a = 0; a < P; ++a) {
+        os << ind << "const int sp" << a << " = " << slot_tab << "[it * " << P << " + " << a << "];\n";
+        os << ind << "const double sg" << a << " = sp" << a << " < " << pr.i_eout << " ? 1.0 : -1.0;\n";
+        os << ind << "const int hb" << a << " = (int)((hc >> sp" << a << ") & 1u);\n";
+        for (int mu = 0; mu < 4; ++mu)
+          os << ind << "const double k" << a << "_" << mu << " = mom[(4 * sp" << a << " + " << mu << ") * N + ptc];\n";
+      }
+    } else {
+      // lane q of a point takes partitions CL i2 + q: the loop index stays
+      // uniform, so the table entries are scalar loads and each lane selects
+      // its own; where the count is not a multiple of CL the last round's
+      // spare lanes repeat the last partition and drop their result
+      os << ind << "#pragma unroll 1\n" << ind << "for (int i2 = 0; i2 < " << (nit + CL - 1) / CL << "; ++i2) {\n";
+      ind += "  ";
+      for (int q = 0; q < CL; ++q)
+        os << ind << "const int it" << q << " = " << CL << " * i2 + " << q << " < " << nit << " ? " << CL << " * i2 + " << q
+           << " : " << nit - 1 << ";\n";
+      for (int a = 0; a < P; ++a) {
+        for (int q = 0; q < CL; ++q)
+          os << ind << "int x" << q << "_" << a << " = " << ix_tab << "[it" << q << " * " << P << " + " << a
+             << "]; asm volatile(\"\" : \"+s\"(x" << q << "_" << a << "));\n";
+        std::string sel = "x" + std::to_string(CL - 1) + "_" + std::to_string(a);
+        for (int q = CL - 2; q >= 0; --q)
+          sel = "q_ == " + std::to_string(q) + " ? x" + std::to_string(q) + "_" + std::to_string(a) + " : (" + sel + ")";
+        os << ind << "const int ix" << a << " = " << sel << ";\n";
+        if (!k_lds) {
+          const int nin = pr.i_eout - 1;
+          os << ind << "const int sp" << a << " = ix" << a << " + (ix" << a << " < " << nin << " ? 1 : 2);\n";
+          os << ind << "const double sg" << a << " = ix" << a << " < " << nin << " ? 1.0 : -1.0;\n";
+          os << ind << "const double* const kp" << a << " = mom + (long long)(4 * sp" << a << ") * N + ptc;\n";
+          for (int mu = 0; mu < 4; ++mu)
+            os << ind << "const double k" << a << "_" << mu << " = kp" << a << "[" << mu << " * N];\n";
+        }
+      }
+      if (nit % CL)
+        for (auto& kv : acc_of_sum)
+          os << ind << "const qx::cx<double> As" << kv.second << " = A" << kv.second << ";\n";
     }
     std::fill(done.begin(), done.end(), 0);
     kdone.clear();
@@ -548,9 +678,24 @@ struct Emitter {
     bool was_local = (v.order & 4) != 0;
     (void)was_local;
     forward_block_inner(key, part[key]);
-    st.flops_per_point = f0 + (st.flops_per_point - f0) * nit;
+    // per lane: the loop's share of the partitions (the caller multiplies by
+    // the lanes of a point)
+    st.flops_per_point = f0 + pre + (st.flops_per_point - f0) * ((nit + CL - 1) / CL);
+    if (cur_cache && nit % CL) {
+      os << ind << "if (" << CL << " * i2 + q_ >= " << nit << ") {";
+      for (auto& kv : acc_of_sum) os << " A" << kv.second << " = As" << kv.second << ";";
+      os << " }\n";
+    }
     ind = outer;
     os << ind << "}\n";
+    if (cur_cache) {
+      // the point's lanes' partial amplitudes
+      for (int o = 1; o < CL; o <<= 1)
+        for (auto& kv : acc_of_sum)
+          os << ind << "A" << kv.second << ".r += __shfl_xor(A" << kv.second << ".r, " << o << "); A" << kv.second
+             << ".i += __shfl_xor(A" << kv.second << ".i, " << o << ");\n";
+      st.flops_per_point += 2.0 * __builtin_ctz(CL) * (double)acc_of_sum.size();
+    }
   }
 
   // Body: accumulators, all nodes in partition-grouped order, |A|^2 sums
@@ -1239,15 +1384,42 @@ void check_variant(const Dag& d, const Variant& v) {
       if ((v.enum_mask >> d.proc.photon_particle[a]) & 1)
         throw std::invalid_argument("the partition loop takes photon helicities at run time only");
   if (v.block % 64 != 0 || v.block < 64 || v.block > 1024) throw std::invalid_argument("bad block size");
+  if (((v.order & (256 | 512)) &&
+       ((v.order & 256 && v.order & 512) || !(v.order & 8) || v.mode != HEL_PER_POINT || v.prec != PREC_F64 ||
+        v.lane_mask || v.fixup || d.split < 2 || d.proc.P - d.split < 1 || d.distributed)) ||
+      ((v.order & 1024) && !(v.order & (256 | 512))))
+    throw std::invalid_argument("the one-photon current cache takes FP64 per-point partition loops with split >= 2");
+}
+
+// The one-photon current cache of a variant for BP points per LDS region
+// whose budget is `budget` bytes: sets e's cache fields; throws if even the
+// currents and polarisations do not fit.
+void setup_cache(Emitter& e, const Dag& d, const Variant& v, const std::string& kname, int BP, int64_t budget) {
+  e.cur_cache = true;
+  e.CL = cache_lanes(v);
+  e.BP = BP;
+  e.ix_tab = kname + "_ix";
+  e.row_only = (v.order & 1024) != 0;
+  const int64_t per = (int64_t)d.proc.P * BP * 8;
+  const int ncur = e.row_only ? 8 : 16;
+  if ((ncur + 3) * per > budget) throw std::invalid_argument("the current cache does not fit the LDS");
+  e.k_lds = (ncur + 7) * per <= budget;
 }
 
 }  // namespace
 
+int body_cache_doubles(const Dag& d, const Variant& v) {
+  if (!(v.order & (256 | 512))) return 0;
+  Emitter e(d, v);
+  setup_cache(e, d, v, "", 64 / cache_lanes(v), kBodyCacheBytes);
+  return ((e.row_only ? 8 : 16) + 3 + (e.k_lds ? 4 : 0)) * d.proc.P * e.BP;
+}
+
 std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* stats) {
   check_variant(d, v);
   Emitter e(d, v);
-  const int LB = popc(v.lane_mask);
-  const int G = 1 << LB;
+  const int G = lanes_per_point(v);
+  const int LB = __builtin_ctz(G);
   std::ostringstream& os = e.os;
   os << "// generated by qedx: " << variant_tag(v, d.proc.n_out, d.proc.n_in) << "\n";
   os << "#include <hip/hip_runtime.h>\n";
@@ -1262,6 +1434,14 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     e.slot = true;
     e.pol_lds = true;
     e.slot_tab = kname + "_slots";
+    if (v.order & (256 | 512)) {
+      // polarisations (3), currents (16, or 8 for the e-_in side only) and
+      // momenta (4) per photon and point; the momenta only where the
+      // workgroups that min_waves asks for still fit the 160 KB of LDS of a
+      // compute unit (4 SIMDs)
+      const int64_t budget = (int64_t)160 * 1024 * v.block / (256 * std::max(1, v.min_waves));
+      setup_cache(e, d, v, kname, v.block / cache_lanes(v), budget);
+    }
     e.emit_slot_table();
   }
   e.mj_tab = kname + "_mjperm";
@@ -1286,7 +1466,9 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
   if (v.fixup) os << "  int fixflag = 0;\n";
   std::string hrt = v.mode == HEL_PER_POINT ? "hel[ptc]" : Emitter::deposit("sub", v.lane_mask);
   e.lane_work(hrt);
-  for (int o = 1; o < G; o <<= 1) os << "  acc += __shfl_xor(acc, " << o << ");\n";
+  // helicity lanes hold parts of the sum (the cache's two lanes hold the
+  // same |A|^2, their amplitudes already combined)
+  for (int o = e.CL; o < G; o <<= 1) os << "  acc += __shfl_xor(acc, " << o << ");\n";
   if (v.fixup)
     // a point the FP32 pass cannot resolve is marked in place with a negative
     // value (|M|^2 itself is never negative); the FP64 pass below finds it
@@ -1301,8 +1483,13 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     std::string decl;
     if (e.lds_slots > 0)
       decl = "  __shared__ " + e.T + " qx_lds[" + std::to_string(e.lds_slots * 8 * v.block) + "];\n";
-    if (e.pol_lds)
+    if (e.cur_cache) {
+      decl += "  __shared__ double qx_pol[" + std::to_string(3 * d.proc.P * e.BP) + "];\n";
+      decl += "  __shared__ double qx_cur[" + std::to_string((e.row_only ? 8 : 16) * d.proc.P * e.BP) + "];\n";
+      if (e.k_lds) decl += "  __shared__ double qx_k[" + std::to_string(4 * d.proc.P * e.BP) + "];\n";
+    } else if (e.pol_lds) {
       decl += "  __shared__ " + e.PT + " qx_pol[" + std::to_string(3 * d.proc.npart * v.block) + "];\n";
+    }
     if (e.mfma_join()) decl += "  __shared__ double qx_mj[" + std::to_string(4 * 64 * Emitter::kMjStride) + "];\n";
     size_t at = src.find(lds_mark);
     src.replace(at, lds_mark.size(), decl);
@@ -1599,6 +1786,11 @@ std::string emit_body_function(const Dag& d, const Variant& v, const std::string
     e.slot = true;
     e.pol_lds = pol_param;
     e.slot_tab = fname + "_slots";
+    if (v.order & (256 | 512)) {
+      setup_cache(e, d, v, fname, 64 / cache_lanes(v), kBodyCacheBytes);
+      e.body_mode = true;
+      e.pol_lds = true;
+    }
     e.emit_slot_table();
   }
   if (v.fixup) {
@@ -1608,13 +1800,20 @@ std::string emit_body_function(const Dag& d, const Variant& v, const std::string
   }
   os << "static __device__ double " << fname
      << "(const double* __restrict__ mom, long long N, long long ptc, unsigned hrt_in"
-     << (e.pol_lds ? ", " + e.PT + "* __restrict__ qx_pol" : std::string()) << (v.fixup ? ", int& fixflag, double fix_kappa" : "")
-     << ")\n{\n";
+     << (e.cur_cache ? ", double* __restrict__ qx_c, int tpt, unsigned sub"
+                     : e.pol_lds ? ", " + e.PT + "* __restrict__ qx_pol" : std::string())
+     << (v.fixup ? ", int& fixflag, double fix_kappa" : "") << ")\n{\n";
+  if (e.cur_cache) {
+    const int P = d.proc.P, ncur = e.row_only ? 8 : 16;
+    os << "  double* const qx_pol = qx_c;\n";
+    os << "  double* const qx_cur = qx_c + " << 3 * P * e.BP << ";\n";
+    if (e.k_lds) os << "  double* const qx_k = qx_c + " << (3 + ncur) * P * e.BP << ";\n";
+  }
   if (!e.local() && !e.slot) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";
   e.lane_work("hrt_in");
   os << "  return acc;\n}\n";
-  e.st.flops_per_point *= (double)(1 << popc(v.lane_mask)) * (double)(1 << popc(v.loop_mask));
+  e.st.flops_per_point *= (double)lanes_per_point(v) * (double)(1 << popc(v.loop_mask));
   if (stats) *stats = e.st;
   return os.str();
 }

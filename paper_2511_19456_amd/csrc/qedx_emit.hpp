@@ -33,6 +33,13 @@ struct Variant {
   int fixup = 0;        // 1: FP32C per-point kernel flags ill-conditioned points for an FP64 pass
 };
 
+// Lanes of a point that share the one-photon current cache of a per-point
+// partition loop and split its partitions: 2 (order flag 256) or 4 (flag
+// 512); 1 without the cache.
+inline int cache_lanes(const Variant& v) { return (v.order & 512) ? 4 : (v.order & 256) ? 2 : 1; }
+// Lanes per phase-space point of an eval kernel: 2^(lane bits) x cache lanes.
+inline int lanes_per_point(const Variant& v) { return (1 << __builtin_popcount(v.lane_mask)) * cache_lanes(v); }
+
 // Points scanned by one workgroup of the FP64 fix-up pass.
 constexpr int kFixRange = 4096;
 
@@ -99,8 +106,19 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
 // With pol_param and a partition slot loop (order & 8) the body also takes
 // (..., T* qx_pol) after hrt: per-lane LDS of 3 npart x (threads per
 // workgroup, 256) values for the photon polarisations, hoisted out of the loop.
+// With the one-photon current cache (order & (256 | 512)) the body instead
+// takes (..., double* qx_c, int tpt, unsigned sub) after hrt: the calling
+// wave's LDS region of body_cache_doubles() values, the point's slot in it
+// (lane / cache lanes) and the lane's index among its point's lanes; every
+// lane of the point returns the point's |A|^2.
 std::string emit_body_function(const Dag& d, const Variant& v, const std::string& fname, EmitStats* st,
                                bool pol_param = false);
+// LDS bytes a wave's region may take (4 waves of a 256-lane workgroup share
+// the 160 KB of a compute unit).
+constexpr int64_t kBodyCacheBytes = 40 * 1024;
+// Doubles of a wave's LDS region for a body with the current cache (64 /
+// cache lanes points), 0 without it.
+int body_cache_doubles(const Dag& d, const Variant& v);
 
 // Element type ("double" or "float") of the per-lane photon polarisation LDS
 // of slot-loop kernels and bodies: FP64 unless an FP32C variant turns off its

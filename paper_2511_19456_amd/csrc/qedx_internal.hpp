@@ -54,7 +54,7 @@ qed_status get_code_object(const std::string& tag, const std::string& src, std::
                            bool& hit, double& ms);
 std::string cache_dir();
 // Kernel shape the library uses for (n, mode, prec) when the caller gives none.
-qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, qedx::Variant& v);
+qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, int rewrite, qedx::Variant& v);
 // Launch of the fused gradient kernel (n <= 3).
 qed_status grad_fused(const qed_process* p, const double* uniforms, double sqrt_s, int64_t N, double* out_logm2,
                       double* out_grad, void* stream);

@@ -269,12 +269,21 @@ static void default_variant(int n, int nin, qed_hel_mode mode, qed_precision pre
   // per-point kernels a run-time loop over the partitions around one
   // canonical block (compact code, seconds to compile even at P = 7).
   v.order = P >= 5 ? (mode == QED_HEL_PER_POINT ? 8 : 4) : 0;
-  // 6 photons, one configuration per point, FP64: two waves per SIMD fit
-  // with 12 bytes of spill (258 registers otherwise): 1.76 against 1.84 ms
-  // on 2^20 points; the other shapes measured slower with the limit (5
-  // photons 0.57 against 0.54 ms, 7 photons and the helicity sums spill
-  // hundreds of bytes)
-  v.min_waves = (mode == QED_HEL_PER_POINT && prec == QED_FP64 && P == 6 && !rewrite) ? 2 : 0;
+  // One configuration per point, FP64, node-reduced, 5..7 photons: the
+  // partition loop with the one-photon current cache (each photon's
+  // one-photon currents computed once per point into LDS, the partitions
+  // split between the lanes of a point).  Measured on 2^20 points (2^18 at
+  // 7 photons) against the loop without it: 5 photons, 2 lanes, the e-_in
+  // side cached (170 VGPRs, 77 KB LDS: two waves per SIMD) 0.445 against
+  // 0.548 ms (both sides cached: 0.512 ms, one wave per SIMD; 4 lanes:
+  // 0.63-0.74 ms); 6 photons, 4 lanes, both sides (218 VGPRs, two waves per
+  // SIMD) 1.53 against 1.82 ms (2 lanes 1.62; e-_in side only 1.67);
+  // 7 photons, 4 lanes, both sides 2.02 against 2.19 ms (2 lanes 2.12)
+  v.min_waves = 0;
+  if (mode == QED_HEL_PER_POINT && prec == QED_FP64 && !rewrite && P >= 5 && P <= 7) {
+    v.order = P == 5 ? (8 | 256 | 1024) : (8 | 512);
+    v.min_waves = P <= 6 ? 2 : 0;
+  }
   if (mode == QED_HEL_SUM) {
     uint32_t all = (1u << npart) - 1;
     // electron spins over lanes; photon polarisations shared in the graph
@@ -354,6 +363,7 @@ static qed_status make_variant_shape(int n, int nin, qed_hel_mode mode, qed_prec
       v.partial_steps = qv->partial_steps;
       v.partial_seed = qv->partial_seed;
       v.order = 0;
+      v.min_waves = qv->min_waves;
       if (!qv->split) v.split = P / 2;  // the join position of the Table I graphs
     }
     if (mode == QED_HEL_SUM && (qv->lane_bits || qv->loop_bits)) {
@@ -434,7 +444,7 @@ static qed_status build_source(int n, int nin, qed_hel_mode mode, qed_precision 
   info.n = n;
   info.mode = mode;
   info.precision = prec;
-  info.lanes_per_point = 1 << __builtin_popcount(v.lane_mask);
+  info.lanes_per_point = lanes_per_point(v);
   info.block = v.block;
   std::string tag = variant_tag(v, n, nin);
   snprintf(info.kernel_tag, sizeof info.kernel_tag, "%s", tag.c_str());
@@ -873,7 +883,11 @@ qed_status grad_fused(const qed_process* p, const double* uniforms, double sqrt_
   void* args[] = {(void*)&uniforms, (void*)&sqrt_s, (void*)&n, (void*)&out_logm2, (void*)&out_grad};
   return launch(p->f_grad, N * (int64_t)p->grad_lanes, p->grad_block, stream, args);
 }
-qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, qedx::Variant& v) {
-  return make_variant(n, 1, mode, prec, nullptr, v);
+qed_status default_process_variant(int n, qed_hel_mode mode, qed_precision prec, int rewrite, qedx::Variant& v) {
+  if (!rewrite) return make_variant(n, 1, mode, prec, nullptr, v);
+  qed_variant q;
+  std::memset(&q, 0, sizeof q);
+  q.rewrite = 1;
+  return make_variant(n, 1, mode, prec, &q, v);
 }
 }  // namespace qedx_rt

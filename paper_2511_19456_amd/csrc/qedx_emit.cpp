@@ -251,7 +251,7 @@ struct Emitter {
     if (cur_cache && n.kind == Kind::S1 && popc(n.mask) == 1 && (n.side == 0 || !row_only)) {
       // a one-photon current: read from the per-point cache
       const std::string ix = "ix" + std::to_string(__builtin_ctz(n.mask));
-      os << ind << "const qx::sp4<double> n" << c << " = {{";
+      os << ind << "const qx::sp4<" << T << "> n" << c << " = {{";
       for (int k = 0; k < 4; ++k)
         os << (k ? ", " : "") << "{" << cache_cur(n.side, ix, 2 * k) << ", " << cache_cur(n.side, ix, 2 * k + 1) << "}";
       os << "}};\n";
@@ -272,14 +272,21 @@ struct Emitter {
           os << ind << "const qx::sp4<" << TU << "> " << nu << " = qx::" << (p == pr.i_ein ? "u_in" : "ubar_out") << "<"
              << TU << ">(" << m << "0, " << m << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", 1.0);\n";
           if (d1) os << ind << "const qx::sp4<float> " << nm << " = qx::to_f(" << nu << ");\n";
+        } else if (cur_cache) {
+          // polarisation from the per-point cache, in the graph's type (the
+          // FP64 first steps that need it in FP64 are cached themselves)
+          os << ind << "const qx::pol3<" << T << "> " << nm << " = {";
+          for (int c = 0; c < 3; ++c) os << (c ? ", " : "") << cache_pol("ix" + std::to_string(slot_of(p)), c);
+          os << "};\n";
+          st.flops_per_point += 16;
+          ++st.n_U;
+          break;
         } else if (slot && pol_lds) {
           std::string sp = "sp" + std::to_string(slot_of(p));
           os << ind << "const qx::pol3<" << TU << "> " << nu << " = {";
           for (int c = 0; c < 3; ++c)
             os << (c ? ", " : "") << (PT != TU ? "(" + TU + ")" : std::string())
-               << (cur_cache ? cache_pol("ix" + std::to_string(slot_of(p)), c)
-                             : "qx_pol[(3 * " + sp + " + " + std::to_string(c) + ") * " + std::to_string(v.block) +
-                                   " + threadIdx.x]");
+               << "qx_pol[(3 * " << sp << " + " << c << ") * " << v.block << " + threadIdx.x]";
           os << "};\n";
           if (d1) os << ind << "const qx::pol3<float> " << nm << " = qx::to_f(" << nu << ");\n";
         } else {
@@ -608,7 +615,7 @@ struct Emitter {
       os << ind << "      double k_[4];\n";
       os << ind << "      for (int mu = 0; mu < 4; ++mu) k_[mu] = mom[(4 * pp + mu) * N + ptc];\n";
       os << ind << "      const qx::pol3<double> e_ = qx::pol<double>(k_[1], k_[2], k_[3], (int)((hc >> pp) & 1u));\n";
-      for (int c = 0; c < 3; ++c) os << ind << "      " << cache_pol("a", c) << " = e_.e" << (c + 1) << ";\n";
+      for (int c = 0; c < 3; ++c) os << ind << "      " << cache_pol("a", c) << " = (" << T << ")e_.e" << (c + 1) << ";\n";
       if (k_lds)
         for (int mu = 0; mu < 4; ++mu) os << ind << "      " << cache_k("a", mu) << " = s_ * k_[" << mu << "];\n";
       os << ind << "      const qx::sp4<double> r_ = qx::sL<double>(qx::vL<double>(ue_, e_), qx::prop_from<double>("
@@ -618,8 +625,9 @@ struct Emitter {
            << mref(eout) << ", s_ * k_[0], s_ * k_[1], s_ * k_[2], s_ * k_[3], -1.0, 1.0));\n";
       for (int side = 0; side < (row_only ? 1 : 2); ++side)
         for (int k = 0; k < 4; ++k)
-          os << ind << "      " << cache_cur(side, "a", 2 * k) << " = " << (side ? "c_" : "r_") << ".c[" << k << "].r; "
-             << cache_cur(side, "a", 2 * k + 1) << " = " << (side ? "c_" : "r_") << ".c[" << k << "].i;\n";
+          os << ind << "      " << cache_cur(side, "a", 2 * k) << " = (" << T << ")" << (side ? "c_" : "r_") << ".c[" << k
+             << "].r; " << cache_cur(side, "a", 2 * k + 1) << " = (" << T << ")" << (side ? "c_" : "r_") << ".c[" << k
+             << "].i;\n";
       os << ind << "    }\n" << ind << "  }\n" << ind << "}\n";
       if (body_mode)
         wave_sync();
@@ -666,8 +674,12 @@ struct Emitter {
         }
       }
       if (nit % CL)
-        for (auto& kv : acc_of_sum)
-          os << ind << "const qx::cx<double> As" << kv.second << " = A" << kv.second << ";\n";
+        for (auto& kv : acc_of_sum) {
+          const int a = kv.second;
+          os << ind << "const qx::cx<" << T << "> As" << a << " = A" << a << ";\n";
+          if (v.prec != PREC_F64) os << ind << "const qx::cx<float> Cs" << a << " = C" << a << ";\n";
+          if (abs_sum) os << ind << "const float Ss" << a << " = S" << a << ";\n";
+        }
     }
     std::fill(done.begin(), done.end(), 0);
     kdone.clear();
@@ -683,12 +695,17 @@ struct Emitter {
     st.flops_per_point = f0 + pre + (st.flops_per_point - f0) * ((nit + CL - 1) / CL);
     if (cur_cache && nit % CL) {
       os << ind << "if (" << CL << " * i2 + q_ >= " << nit << ") {";
-      for (auto& kv : acc_of_sum) os << " A" << kv.second << " = As" << kv.second << ";";
+      for (auto& kv : acc_of_sum) {
+        const int a = kv.second;
+        os << " A" << a << " = As" << a << ";";
+        if (v.prec != PREC_F64) os << " C" << a << " = Cs" << a << ";";
+        if (abs_sum) os << " S" << a << " = Ss" << a << ";";
+      }
       os << " }\n";
     }
     ind = outer;
     os << ind << "}\n";
-    if (cur_cache) {
+    if (cur_cache && v.prec == PREC_F64) {
       // the point's lanes' partial amplitudes
       for (int o = 1; o < CL; o <<= 1)
         for (auto& kv : acc_of_sum)
@@ -730,10 +747,17 @@ struct Emitter {
       if (v.prec == PREC_F64) {
         os << ind << "acc += A" << a << ".r * A" << a << ".r + A" << a << ".i * A" << a << ".i;\n";
       } else {
-        os << ind << "{ const double ar = (double)A" << a << ".r + (double)C" << a << ".r, ai = (double)A" << a
-           << ".i + (double)C" << a << ".i; acc += ar * ar + ai * ai;";
-        if (abs_sum)
-          os << " if (!((double)S" << a << " <= fix_kappa * fix_kappa * (ar * ar + ai * ai))) fixflag = 1;";
+        os << ind << "{ double ar = (double)A" << a << ".r + (double)C" << a << ".r, ai = (double)A" << a
+           << ".i + (double)C" << a << ".i;";
+        if (abs_sum) os << " double sa = (double)S" << a << ";";
+        if (cur_cache)
+          // the point's lanes' partial sums, combined in FP64
+          for (int o = 1; o < CL; o <<= 1) {
+            os << " ar += __shfl_xor(ar, " << o << "); ai += __shfl_xor(ai, " << o << ");";
+            if (abs_sum) os << " sa += __shfl_xor(sa, " << o << ");";
+          }
+        os << " acc += ar * ar + ai * ai;";
+        if (abs_sum) os << " if (!(sa <= fix_kappa * fix_kappa * (ar * ar + ai * ai))) fixflag = 1;";
         os << " }\n";
       }
       st.flops_per_point += 4;
@@ -1385,10 +1409,10 @@ void check_variant(const Dag& d, const Variant& v) {
         throw std::invalid_argument("the partition loop takes photon helicities at run time only");
   if (v.block % 64 != 0 || v.block < 64 || v.block > 1024) throw std::invalid_argument("bad block size");
   if (((v.order & (256 | 512)) &&
-       ((v.order & 256 && v.order & 512) || !(v.order & 8) || v.mode != HEL_PER_POINT || v.prec != PREC_F64 ||
-        v.lane_mask || v.fixup || d.split < 2 || d.proc.P - d.split < 1 || d.distributed)) ||
+       ((v.order & 256 && v.order & 512) || !(v.order & 8) || v.mode != HEL_PER_POINT || (v.order & 64) ||
+        v.lane_mask || d.split < 2 || d.proc.P - d.split < 1 || d.distributed)) ||
       ((v.order & 1024) && !(v.order & (256 | 512))))
-    throw std::invalid_argument("the one-photon current cache takes FP64 per-point partition loops with split >= 2");
+    throw std::invalid_argument("the one-photon current cache takes per-point partition loops with split >= 2");
 }
 
 // The one-photon current cache of a variant for BP points per LDS region
@@ -1400,10 +1424,18 @@ void setup_cache(Emitter& e, const Dag& d, const Variant& v, const std::string& 
   e.BP = BP;
   e.ix_tab = kname + "_ix";
   e.row_only = (v.order & 1024) != 0;
-  const int64_t per = (int64_t)d.proc.P * BP * 8;
+  const int64_t per = (int64_t)d.proc.P * BP;                  // photon-points
+  const int tsz = v.prec == PREC_F64 ? 8 : 4;                   // currents, polarisations
   const int ncur = e.row_only ? 8 : 16;
-  if ((ncur + 3) * per > budget) throw std::invalid_argument("the current cache does not fit the LDS");
-  e.k_lds = (ncur + 7) * per <= budget;
+  if ((ncur + 3) * tsz * per > budget) throw std::invalid_argument("the current cache does not fit the LDS");
+  e.k_lds = ((ncur + 3) * tsz + 4 * 8) * per <= budget;        // momenta in FP64
+}
+
+// Bytes of the cache's three arrays for BP points (polarisations and
+// currents in the graph's type, momenta in FP64).
+int64_t cache_bytes(const Emitter& e, const Dag& d, const Variant& v) {
+  const int tsz = v.prec == PREC_F64 ? 8 : 4;
+  return (((e.row_only ? 8 : 16) + 3) * tsz + (e.k_lds ? 32 : 0)) * (int64_t)d.proc.P * e.BP;
 }
 
 }  // namespace
@@ -1412,7 +1444,7 @@ int body_cache_doubles(const Dag& d, const Variant& v) {
   if (!(v.order & (256 | 512))) return 0;
   Emitter e(d, v);
   setup_cache(e, d, v, "", 64 / cache_lanes(v), kBodyCacheBytes);
-  return ((e.row_only ? 8 : 16) + 3 + (e.k_lds ? 4 : 0)) * d.proc.P * e.BP;
+  return (int)((cache_bytes(e, d, v) + 7) / 8);
 }
 
 std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* stats) {
@@ -1484,8 +1516,8 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     if (e.lds_slots > 0)
       decl = "  __shared__ " + e.T + " qx_lds[" + std::to_string(e.lds_slots * 8 * v.block) + "];\n";
     if (e.cur_cache) {
-      decl += "  __shared__ double qx_pol[" + std::to_string(3 * d.proc.P * e.BP) + "];\n";
-      decl += "  __shared__ double qx_cur[" + std::to_string((e.row_only ? 8 : 16) * d.proc.P * e.BP) + "];\n";
+      decl += "  __shared__ " + e.T + " qx_pol[" + std::to_string(3 * d.proc.P * e.BP) + "];\n";
+      decl += "  __shared__ " + e.T + " qx_cur[" + std::to_string((e.row_only ? 8 : 16) * d.proc.P * e.BP) + "];\n";
       if (e.k_lds) decl += "  __shared__ double qx_k[" + std::to_string(4 * d.proc.P * e.BP) + "];\n";
     } else if (e.pol_lds) {
       decl += "  __shared__ " + e.PT + " qx_pol[" + std::to_string(3 * d.proc.npart * v.block) + "];\n";
@@ -1500,6 +1532,7 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     Variant v64 = v;
     v64.prec = PREC_F64;
     v64.fixup = 0;
+    v64.order &= ~(256 | 512 | 1024);  // one lane per listed point
     EmitStats st64;
     std::ostringstream fx;
     fx << emit_body_function(d, v64, kname + "_b64", &st64) << "\n";
@@ -1805,9 +1838,10 @@ std::string emit_body_function(const Dag& d, const Variant& v, const std::string
      << (v.fixup ? ", int& fixflag, double fix_kappa" : "") << ")\n{\n";
   if (e.cur_cache) {
     const int P = d.proc.P, ncur = e.row_only ? 8 : 16;
-    os << "  double* const qx_pol = qx_c;\n";
-    os << "  double* const qx_cur = qx_c + " << 3 * P * e.BP << ";\n";
-    if (e.k_lds) os << "  double* const qx_k = qx_c + " << (3 + ncur) * P * e.BP << ";\n";
+    // (3 + ncur) P BP is even (BP is a multiple of 16), so qx_k stays 8-byte aligned
+    os << "  " << e.T << "* const qx_pol = (" << e.T << "*)qx_c;\n";
+    os << "  " << e.T << "* const qx_cur = qx_pol + " << 3 * P * e.BP << ";\n";
+    if (e.k_lds) os << "  double* const qx_k = (double*)(qx_cur + " << ncur * P * e.BP << ");\n";
   }
   if (!e.local() && !e.slot) e.load_momenta("mom", "N", "ptc");
   os << "  double acc = 0.0;\n";

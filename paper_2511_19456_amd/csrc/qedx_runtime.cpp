@@ -278,11 +278,14 @@ static void default_variant(int n, int nin, qed_hel_mode mode, qed_precision pre
   // 0.548 ms (both sides cached: 0.512 ms, one wave per SIMD; 4 lanes:
   // 0.63-0.74 ms); 6 photons, 4 lanes, both sides (218 VGPRs, two waves per
   // SIMD) 1.53 against 1.82 ms (2 lanes 1.62; e-_in side only 1.67);
-  // 7 photons, 4 lanes, both sides 2.02 against 2.19 ms (2 lanes 2.12)
+  // 7 photons, 4 lanes, both sides 2.02 against 2.19 ms (2 lanes 2.12).
+  // FP32C (currents and polarisations cached rounded to FP32, computed in
+  // FP64 as the first steps are), same shapes: 0.444 against 0.554 ms, 1.46
+  // against 1.86 ms, 2.22 against 2.93 ms
   v.min_waves = 0;
-  if (mode == QED_HEL_PER_POINT && prec == QED_FP64 && !rewrite && P >= 5 && P <= 7) {
+  if (mode == QED_HEL_PER_POINT && !rewrite && P >= 5 && P <= 7) {
     v.order = P == 5 ? (8 | 256 | 1024) : (8 | 512);
-    v.min_waves = P <= 6 ? 2 : 0;
+    v.min_waves = P == 5 || (P == 6 && prec == QED_FP64) ? 2 : 0;
   }
   if (mode == QED_HEL_SUM) {
     uint32_t all = (1u << npart) - 1;

@@ -164,12 +164,13 @@ def test_default_kernel_shapes():
     # 5 photons, FP64 sum: e-_in spin and 3 photons in the graph, 2 looped
     assert tag(4, "sum", "fp64").startswith("nin1_nout4_p0_m0_e27_l4_o96_")
     # per point: join split ceil(P/2) for 5 and 7 photons, slot loop with the
-    # one-photon current cache (FP64: 2 lanes and the e-_in side at 5
-    # photons, 4 lanes and both sides at 6 and 7); FP32C without it
+    # one-photon current cache (2 lanes and the e-_in side at 5 photons, 4
+    # lanes and both sides at 6 and 7; FP64 and FP32C alike)
     assert tag(4, "per_point", "fp64") == "nin1_nout4_p0_m1_e0_l0_o0_b256_s3_j1_r1288_w2"
     assert tag(5, "per_point", "fp64") == "nin1_nout5_p0_m1_e0_l0_o0_b256_s3_j1_r520_w2"
     assert tag(6, "per_point", "fp64") == "nin1_nout6_p0_m1_e0_l0_o0_b256_s4_j1_r520_w0"
-    assert "_r8_" in tag(5, "per_point", "fp32c")
+    assert tag(5, "per_point", "fp32c") == "nin1_nout5_p1_m1_e0_l0_o0_b256_s3_j1_r520_w0_f1"
+    assert tag(4, "per_point", "fp32c") == "nin1_nout4_p1_m1_e0_l0_o0_b256_s3_j1_r1288_w2_f1"
     assert "_r8_" in tag(4, "per_point", "fp64", rewrite=0, order=8)
     # FP32C per point carries the FP64 pass
     assert tag(5, "per_point", "fp32c").endswith("_f1")

@@ -1532,18 +1532,23 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     Variant v64 = v;
     v64.prec = PREC_F64;
     v64.fixup = 0;
-    v64.order &= ~(256 | 512 | 1024);  // one lane per listed point
+    v64.min_waves = 0;
     EmitStats st64;
     std::ostringstream fx;
     fx << emit_body_function(d, v64, kname + "_b64", &st64) << "\n";
+    // with the one-photon current cache the FP64 body takes CL lanes per
+    // point and its wave's LDS region
+    const int CL = cache_lanes(v64);
+    const int W = body_cache_doubles(d, v64);
     // Each workgroup of 256 lanes owns kFixRange consecutive points: it scans
     // their results for the negative marks, compacts the marked offsets in
     // LDS (one LDS atomic per wave: ballot, then each marked lane's rank
-    // among the marked lanes below it) and recomputes them 256 at a time, so
-    // the FP64 body runs on full waves however sparse the marks are.
+    // among the marked lanes below it) and recomputes them 256 / CL at a
+    // time, so the FP64 body runs on full waves however sparse the marks are.
     fx << "extern \"C\" __global__ void __launch_bounds__(256)\n"
        << kname << "_fix(const double* __restrict__ mom, const unsigned* __restrict__ hel, long long N, "
        << "double* __restrict__ out)\n{\n"
+       << (W ? "  __shared__ double qx_fc[" + std::to_string(4 * W) + "];\n" : std::string())
        << "  __shared__ unsigned fx_list[" << kFixRange << "];\n"
        << "  __shared__ unsigned fx_cnt;\n"
        << "  if (threadIdx.x == 0) fx_cnt = 0u;\n"
@@ -1563,11 +1568,24 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
        << "    }\n"
        << "  }\n"
        << "  __syncthreads();\n"
-       << "  const unsigned cnt = fx_cnt;\n"
-       << "  for (unsigned j = threadIdx.x; j < cnt; j += 256u) {\n"
-       << "    const long long pt = base + (long long)fx_list[j];\n"
-       << "    out[pt] = " << kname << "_b64(mom, N, pt, hel[pt]);\n"
-       << "  }\n}\n";
+       << "  const unsigned cnt = fx_cnt;\n";
+    if (CL == 1) {
+      fx << "  for (unsigned j = threadIdx.x; j < cnt; j += 256u) {\n"
+         << "    const long long pt = base + (long long)fx_list[j];\n"
+         << "    out[pt] = " << kname << "_b64(mom, N, pt, hel[pt]);\n"
+         << "  }\n}\n";
+    } else {
+      // every lane takes part in every round (the body synchronises its wave)
+      const int sh = __builtin_ctz(CL);
+      fx << "  const unsigned sub = threadIdx.x & " << CL - 1 << "u;\n"
+         << "  for (unsigned j0 = 0; j0 < cnt; j0 += " << 256 / CL << "u) {\n"
+         << "    const unsigned j = j0 + (threadIdx.x >> " << sh << ");\n"
+         << "    const long long pt = base + (long long)fx_list[j < cnt ? j : cnt - 1u];\n"
+         << "    const double r = " << kname << "_b64(mom, N, pt, hel[pt], qx_fc + (threadIdx.x >> 6) * " << W
+         << ", (int)((threadIdx.x & 63u) >> " << sh << "), sub);\n"
+         << "    if (j < cnt && sub == 0u) out[pt] = r;\n"
+         << "  }\n}\n";
+    }
     src += fx.str();
   }
   e.st.lines = std::count(src.begin(), src.end(), '\n');

@@ -41,7 +41,7 @@ inline int cache_lanes(const Variant& v) { return (v.order & 512) ? 4 : (v.order
 inline int lanes_per_point(const Variant& v) { return (1 << __builtin_popcount(v.lane_mask)) * cache_lanes(v); }
 
 // Points scanned by one workgroup of the FP64 fix-up pass.
-constexpr int kFixRange = 4096;
+constexpr int kFixRange = 1024;
 
 struct EmitStats {
   double flops_per_point = 0;   // algorithmic FLOPs per phase-space point

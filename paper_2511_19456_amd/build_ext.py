@@ -147,6 +147,9 @@ DEFAULT_KERNELS = [
     (1, 1, 0, dict(n_in=6, rewrite=1)),
     # FP32C per point without the FP64 pass (bench leg and tests)
     (3, 1, 1, dict(fixup=-1)), (5, 1, 1, dict(fixup=-1)),
+    # one-photon current cache shapes the parity tests exercise
+    (4, 1, 0, dict(order=8)), (4, 1, 0, dict(order=264)), (4, 1, 0, dict(order=520)), (5, 1, 0, dict(order=1288)),
+    (6, 1, 0, dict(order=264)), (4, 1, 1, dict(order=520)), (6, 1, 1, dict(order=1288)),
 ]
 
 

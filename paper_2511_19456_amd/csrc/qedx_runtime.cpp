@@ -353,8 +353,13 @@ static qed_status make_variant_shape(int n, int nin, qed_hel_mode mode, qed_prec
   if (qv && !qv->use_defaults) {
     if (qv->block) v.block = qv->block;
     if (qv->split) v.split = qv->split;
+    if (qv->order) {
+      // an explicit schedule drops the default's occupancy hint (made for the
+      // default schedule) unless one is given
+      v.order = qv->order;
+      v.min_waves = 0;
+    }
     if (qv->min_waves) v.min_waves = qv->min_waves;
-    if (qv->order) v.order = qv->order;
     if (qv->rewrite < 0 || qv->rewrite > 1) return fail(QED_ERR_INVALID_ARG, "rewrite must be 0 or 1");
     v.rewrite = qv->rewrite;
     if (qv->partial) {

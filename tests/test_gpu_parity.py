@@ -225,6 +225,33 @@ def test_per_point_n6_fp64(n, sqrt_s, N):
     check_fp64(got, ref, kap, "per point n=6")
 
 
+# One-photon current cache of the per-point partition loop: each lane split
+# and cached side, FP64 and FP32C, partition counts the lanes divide and ones
+# they do not (the last round's spare lanes repeat a partition and drop it).
+@pytest.mark.parametrize("n,sqrt_s,N,order,prec", [
+    (4, 15.0, 333, 8, "fp64"),                # the loop without the cache
+    (4, 15.0, 333, 8 | 256, "fp64"),          # 2 lanes, both sides cached
+    (4, 15.0, 333, 8 | 512, "fp64"),          # 4 lanes over 10 partitions
+    (5, 20.0, 257, 8 | 256 | 1024, "fp64"),   # 2 lanes, e-_in side only
+    (6, 25.0, 67, 8 | 256, "fp64"),           # 35 partitions over 2 lanes
+    (4, 15.0, 333, 8 | 512, "fp32c"),
+    (6, 25.0, 67, 8 | 256 | 1024, "fp32c"),
+])
+def test_current_cache_shapes(n, sqrt_s, N, order, prec):
+    from paper_2511_19456_amd.qedx import make_variant
+    u, hel = inputs.rambo_inputs(29, n, N, with_helicities=True)
+    ref_mom = O.momenta_soa_from_uniforms(u, sqrt_s, n)
+    p = _proc(n, "per_point", prec, make_variant(order=order))
+    assert p.info()["lanes_per_point"] == (4 if order & 512 else 2 if order & 256 else 1)
+    got = p.eval(torch.as_tensor(ref_mom.numpy(), device=DEV),
+                 torch.as_tensor(hel.astype(np.int32), device=DEV)).cpu().numpy()
+    ref, kap = per_point_ref(ref_mom, n, hel)
+    if prec == "fp64":
+        check_fp64(got, ref, kap, f"per point n={n} order={order}")
+    else:
+        assert _rel(got, ref).max() < 1e-4
+
+
 @pytest.mark.parametrize("prec,tile,rewrite", [("fp64", 128, 0), ("fp64", 0, 0), ("fp32c", 0, 0), ("fp64", 256, 1)])
 def test_mixed_batch_matches_per_process_and_oracle(prec, tile, rewrite):
     from paper_2511_19456_amd.qedx import BatchPlan, make_variant

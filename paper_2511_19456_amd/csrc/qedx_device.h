@@ -201,6 +201,27 @@ template <class T> QEDX_HD void comp_acc(cx<T>& s, cx<T>& c, const cx<T>& x) {
 // layout).  Device only; all 64 lanes of the wave must be active.
 // ---------------------------------------------------------------------------
 #if defined(__HIP_DEVICE_COMPILE__)
+// The current held by the partner lane (lane ^ 1): the two lanes of a point
+// that build the e-_in-side currents for one e-_in spin each exchange them,
+// through DPP (quad_perm [1,0,3,2]: one VALU move per 32 bits; measured
+// faster than the LDS permute of __shfl_xor in the helicity-sum kernels).
+// Device only; both lanes of the pair must be active.
+__device__ inline float lane_xor1(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+__device__ inline double lane_xor1(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <class T> __device__ inline sp4<T> lane_xor1(const sp4<T>& a) {
+  sp4<T> o;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o.c[k] = {lane_xor1(a.c[k].r), lane_xor1(a.c[k].i)};
+  return o;
+}
+
 __device__ inline void mfma_join4(const double* stg, int stride, int src, double (&mj)[32]) {
   const int l = (int)(threadIdx.x & 63);
   const int k = l >> 4, b = (l >> 2) & 3, r = l & 3;

@@ -146,6 +146,40 @@ struct Emitter {
   int BP = 0, CL = 1;  // points per workgroup, lanes per point
   bool k_lds = false;  // the signed photon momenta cached too (where LDS allows)
   bool row_only = false;  // order flag 1024: only the e-_in side's currents cached
+  // Shared e-_in side (order flag 2048; SUM kernels whose one lane bit is
+  // the e-_out spin and whose graph enumerates the e-_in spin): both lanes of
+  // a point would build the same e-_in-side currents for both e-_in spins.
+  // Instead each lane builds them for one e-_in spin (its lane bit) and takes
+  // the other spin's leaves from its partner lane.  Lane 1 thereby swaps the
+  // e-_in labels of all its accumulators, which leaves sum |A|^2 unchanged.
+  bool coop = false;
+  std::map<std::pair<int, int>, int> v_of;  // (photon state, current) -> V node
+  std::map<int, int> s1_of;                 // current -> S1 node
+  int u_ein0 = -1;                          // U node of e-_in with spin 0
+  bool ein1(int x) const {  // an e-_in-side value of e-_in spin 1
+    const Node& n = d.nodes[x];
+    const uint32_t b = 1u << pr.i_ein;
+    return coop && n.side == 0 && (n.kind == Kind::V || n.kind == Kind::S1) && (n.cfg_dep & b) && (n.cfg & b);
+  }
+  void build_twins() {
+    for (size_t i = 0; i < d.nodes.size(); ++i) {
+      const Node& n = d.nodes[i];
+      if (n.kind == Kind::V) v_of[{producer(n.in[0]), producer(n.in[1])}] = (int)i;
+      if (n.kind == Kind::S1) s1_of[producer(n.in[0])] = (int)i;
+      if (n.kind == Kind::U && n.particle == pr.i_ein && n.hel == 0) u_ein0 = (int)i;
+    }
+    if (u_ein0 < 0) throw std::invalid_argument("shared e-_in side: no enumerated e-_in spin");
+  }
+  // the same value with e-_in spin 0
+  int twin(int x) const {
+    x = producer(x);
+    const Node& n = d.nodes[x];
+    if (n.kind == Kind::U) return n.particle == pr.i_ein ? u_ein0 : x;
+    if (n.kind == Kind::V) return v_of.at({producer(n.in[0]), twin(n.in[1])});
+    if (n.kind == Kind::S1) return s1_of.at(twin(n.in[0]));
+    throw std::logic_error("shared e-_in side: unexpected node kind");
+  }
+
   // a device-function body of the persistent batch kernel: the cache is the
   // wave's own LDS region (BP = points per wave), tpt and sub are arguments,
   // and the wave synchronises only itself
@@ -231,6 +265,7 @@ struct Emitter {
   std::string name_d(int i) const { return "n" + std::to_string(producer(i)) + "_d"; }
 
   std::string hel_expr(const Node& u) const {
+    if (coop && u.particle == pr.i_ein) return "(int)((hc >> " + std::to_string(pr.i_eout) + ") & 1u)";
     if (u.hel >= 0) return std::to_string((int)u.hel);
     if (slot && slot_of(u.particle) >= 0) return "hb" + std::to_string(slot_of(u.particle));
     return "(int)((hc >> " + std::to_string(u.particle) + ") & 1u)";
@@ -248,6 +283,14 @@ struct Emitter {
     int c = producer(i);
     if (done[c]) return;
     const Node& n = d.nodes[c];
+    if (ein1(c)) {
+      // built by the partner lane as its spin-0 twin
+      const int t = twin(c);
+      emit(t);
+      os << ind << "const qx::sp4<" << T << "> n" << c << " = qx::lane_xor1(" << name(t) << ");\n";
+      done[c] = 1;
+      return;
+    }
     if (cur_cache && n.kind == Kind::S1 && popc(n.mask) == 1 && (n.side == 0 || !row_only)) {
       // a one-photon current: read from the per-point cache
       const std::string ix = "ix" + std::to_string(__builtin_ctz(n.mask));
@@ -531,13 +574,24 @@ struct Emitter {
       return;
     }
     for (int h : hold) emit(h);
-    for (int s : stream) {
+    auto stream_one = [&](int s) {
       emit(s);
       for (int k : dk) {
         auto ops = dot_ops(d.nodes[k]);
         int sp = producer(holdB ? ops.first : ops.second);
         if (sp == s) emit_dot(k);
       }
+    };
+    // with the shared e-_in side each spin-1 leaf follows its spin-0 twin
+    std::map<int, int> after;
+    if (coop && !holdB)
+      for (int s : stream)
+        if (ein1(s) && stream.count(twin(s))) after[twin(s)] = s;
+    for (int s : stream) {
+      if (coop && !holdB && ein1(s) && stream.count(twin(s))) continue;
+      stream_one(s);
+      auto a = after.find(s);
+      if (a != after.end()) stream_one(a->second);
     }
   }
 
@@ -1411,8 +1465,12 @@ void check_variant(const Dag& d, const Variant& v) {
   if (((v.order & (256 | 512)) &&
        ((v.order & 256 && v.order & 512) || !(v.order & 8) || v.mode != HEL_PER_POINT || (v.order & 64) ||
         v.lane_mask || d.split < 2 || d.proc.P - d.split < 1 || d.distributed)) ||
-      ((v.order & 1024) && !(v.order & (256 | 512))))
-    throw std::invalid_argument("the one-photon current cache takes per-point partition loops with split >= 2");
+      ((v.order & 1024) && !(v.order & (256 | 512))) ||
+      ((v.order & 2048) && (v.mode != HEL_SUM || v.lane_mask != (1u << d.proc.i_eout) ||
+                            !((v.enum_mask >> d.proc.i_ein) & 1u) || (v.order & (8 | 16 | 128)) || d.distributed)))
+    throw std::invalid_argument(
+        "the one-photon current cache takes per-point partition loops with split >= 2; the shared e-_in side "
+        "takes helicity sums with the e-_out spin as the one lane bit and the e-_in spin in the graph");
 }
 
 // The one-photon current cache of a variant for BP points per LDS region
@@ -1475,6 +1533,10 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
       setup_cache(e, d, v, kname, v.block / cache_lanes(v), budget);
     }
     e.emit_slot_table();
+  }
+  if (v.order & 2048) {
+    e.coop = true;
+    e.build_twins();
   }
   e.mj_tab = kname + "_mjperm";
   const std::string mj_mark = "//@MJTAB@\n";

@@ -155,14 +155,15 @@ def test_default_kernel_shapes():
         src = Q.emit_source(n, mode, prec, Q.make_variant(**kw) if kw else None)
         return src.splitlines()[0].split("generated by qedx: ")[1]
     # 4 photons, FP64 sum: e-_out spin on lanes, one block per partition
-    assert tag(3, "sum", "fp64") == "nin1_nout3_p0_m0_e59_l4_o0_b256_s2_j1_r4_w0"
+    # (the two lanes share the e-_in side: order flag 2048)
+    assert tag(3, "sum", "fp64") == "nin1_nout3_p0_m0_e59_l4_o0_b256_s2_j1_r2052_w0"
     # FP32C and the distributive rewrite keep both spins on lanes, shared block
     assert "_l5_o0_" in tag(3, "sum", "fp32c") and "_r0_" in tag(3, "sum", "fp32c")
     assert "_l5_o0_" in tag(3, "sum", "fp64", rewrite=1)
     # an explicit coverage keeps the shared block unless an order is given
     assert "_l7_o0_" in tag(3, "sum", "fp64", lane_bits=7) and "_r0_" in tag(3, "sum", "fp64", lane_bits=7)
     # 5 photons, FP64 sum: e-_in spin and 3 photons in the graph, 2 looped
-    assert tag(4, "sum", "fp64").startswith("nin1_nout4_p0_m0_e27_l4_o96_")
+    assert tag(4, "sum", "fp64") == "nin1_nout4_p0_m0_e27_l4_o96_b256_s2_j1_r2052_w0"
     # per point: join split ceil(P/2) for 5 and 7 photons, slot loop with the
     # one-photon current cache (2 lanes and the e-_in side at 5 photons, 4
     # lanes and both sides at 6 and 7; FP64 and FP32C alike)

@@ -231,8 +231,9 @@ typedef struct {
  * signature).  The plan copies the segment table to the device, allocates a
  * 256-byte tile counter, and instantiates a HIP graph of two kernel nodes
  * (counter clear, persistent kernel).  FP32C plans (per-point processes with
- * the FP64 fix-up) also allocate a list of 4(1 + 2 x total points) bytes and
- * add two nodes (list clear, FP64 pass over the listed points); the threshold
+ * the FP64 fix-up) also allocate 4(64 + total points) bytes (a counter and a
+ * point list per segment) and add two nodes (counter clear, FP64 pass over
+ * the listed points, segment by segment); the threshold
  * is the first segment's process's fix_kappa, and the total must stay below
  * 2^31 points.  The segment buffers must stay valid while the plan is
  * launched.  Plans are not thread-safe: launches of one plan on overlapping

@@ -185,7 +185,7 @@ qed_status qed_rambo(const qed_process* p, const double* uniforms, double sqrt_s
  * kernel per photon partition, and the RAMBO adjoint.  The workspace is
  * caller-owned device memory, 8-byte aligned, of workspace_bytes bytes: its
  * size sets the chunk (qed_eval_grad_workspace_size gives the size for the
- * largest chunk, about 2.5 KB per point at n = 4, at most 320 MB); less than
+ * largest chunk, about 3.5 KB per point at n = 4, at most 512 MB); less than
  * 64 points' worth (or N's, if smaller) is INVALID_ARG.  Calls that overlap
  * need workspaces of their own.  `hel` must be NULL.  UNSUPPORTED for
  * PER_POINT or FP32C processes and for n >= 5. */

@@ -1179,7 +1179,7 @@ struct Emitter {
         const std::string side = n.side == 0 ? "L" : "R", other = n.side == 0 ? "R" : "L";
         std::string y = fwd(n.in[1]);
         os << ind << "qx::v" << side << "_ge<double>(" << w << ", " << y << ", ge" << producer(n.in[0]) << ");\n";
-        std::string wy = tmpname("w");
+          std::string wy = tmpname("w");
         os << ind << "const qx::sp4<double> " << wy << " = qx::v" << other << "<double>(" << w << ", "
            << name(n.in[0]) << ");\n";
         st.flops_per_point += 48 + 40;
@@ -1308,6 +1308,20 @@ struct Emitter {
     }
   }
 
+  // Split adjoint kernels (grad_phase): 0 = the whole partition sweep; 1 =
+  // the e-_out-side walk, storing that side's leaf sums per pattern to sb;
+  // 2 = the e-_in-side walk, with those sums loaded from sb.  Each of the
+  // two kernels holds only its own walk's state (the seeds are needed only
+  // before the walk of phase 1).  sb holds, per lane of the launch
+  // (NL = N x lanes) and loop iteration lp, 8 doubles per pattern:
+  // sb[((lp * npb + i) * 8 + w) * NL + gid].
+  int grad_phase = 0;
+  std::string sb_ref(int i, int w) const {
+    return "sb[((lp * " + std::to_string(sb_npb) + "u + " + std::to_string(i) + "u) * 8u + " + std::to_string(w) +
+           "u) * NL + gidc]";
+  }
+  int sb_npb = 0;
+
   void grad_block(uint32_t key, const std::vector<int>& dk) {
     collect_block(dk);
     os << ind << "// adjoint: photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << "\n";
@@ -1327,6 +1341,17 @@ struct Emitter {
     if (factored) {
       for (auto& kv : memB) patB.insert(kv.second);
       for (auto& kv : memJ) patJ.insert(kv.second);
+    }
+    if (factored && grad_phase == 2) {
+      // the e-_out side's leaf sums, from the phase-1 kernel
+      int i = 0;
+      for (uint32_t q : patB) {
+        os << ind << "const qx::sp4<double> SB" << q << " = {{";
+        for (int k = 0; k < 4; ++k) os << (k ? ", " : "") << "{" << sb_ref(i, 2 * k) << ", " << sb_ref(i, 2 * k + 1) << "}";
+        os << "}};\n";
+        ++i;
+      }
+    } else if (factored) {
       // column sums per pattern, from a forward walk of the column trie in a
       // scope of its own (its currents die with it; the column sweep below
       // recomputes them)
@@ -1358,6 +1383,7 @@ struct Emitter {
     }
     // e-_out side trie (dots at its leaves), then e-_in side trie
     for (int pass = 0; pass < 2; ++pass) {
+      if ((grad_phase == 1 && pass == 1) || (grad_phase == 2 && pass == 0)) continue;
       int root_particle = pass == 0 ? pr.i_eout : pr.i_ein;
       if (pass == 1 && factored)
         for (uint32_t q : patJ) emit_seed("W" + std::to_string(q), q, "SB", patB);
@@ -1373,6 +1399,18 @@ struct Emitter {
              << hel_expr(n) << ", 1.0, w" << r << ", g);\n";
           for (int mu = 0; mu < 4; ++mu) os << ind << "  " << gmref(pr.i_eout, mu) << " += g[" << mu << "];\n";
           os << ind << "}\n";
+        }
+      }
+      if (pass == 0 && grad_phase == 1) {
+        // the e-_out side's leaf sums for the phase-2 kernel
+        int i = 0;
+        for (uint32_t q : patB) {
+          os << ind << "if (gid < NL) {";
+          for (int k = 0; k < 4; ++k)
+            os << " " << sb_ref(i, 2 * k) << " = SB" << q << ".c[" << k << "].r; " << sb_ref(i, 2 * k + 1) << " = SB" << q
+               << ".c[" << k << "].i;";
+          os << " }\n";
+          ++i;
         }
       }
     }
@@ -1791,7 +1829,7 @@ std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& k
 }
 
 std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const std::string& kprefix, int* count,
-                                           EmitStats* stats) {
+                                           EmitStats* stats, int* sb_doubles) {
   check_variant(d, v);
   if (v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4) || (v.order & (8 | 16)))
     throw std::invalid_argument("adjoint kernels take SUM, FP64, local blocks");
@@ -1809,8 +1847,26 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
   std::ostringstream all;
   EmitStats tot;
   int t = 0;
+  int sb_max = 0;
   for (uint32_t key : order) {
+    // factored partitions: two kernels (e-_out-side walk, e-_in-side walk)
+    int npb = 0;
+    if (!d.distributed) {
+      Emitter pe(d, v);
+      std::vector<int> ps = pe.sum_nodes();
+      for (size_t a = 0; a < ps.size(); ++a) pe.acc_of_sum[ps[a]] = (int)a;
+      pe.collect_block(part[key]);
+      if (pe.factor_block(part[key])) {
+        std::set<uint32_t> pb;
+        for (auto& kv : pe.memB) pb.insert(kv.second);
+        npb = (int)pb.size();
+      }
+    }
+    sb_max = std::max(sb_max, npb);
+    for (int phase = npb ? 1 : 0; phase <= (npb ? 2 : 0); ++phase) {
     Emitter e(d, v);
+    e.grad_phase = phase;
+    e.sb_npb = npb;
     e.mom_src = 0;       // momenta reloaded per block from the workspace
     e.gm_in_lds = true;  // gradient accumulators in per-lane LDS slots
     e.gq_in_lds = !d.distributed;  // propagator gradients per propagator, flushed once
@@ -1819,7 +1875,7 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     std::ostringstream& os = e.os;
     os << "extern \"C\" __global__ void __launch_bounds__(" << v.block << ")\n" << kprefix << "_" << t
        << "(const double* __restrict__ mom, const double* __restrict__ amp, const double* __restrict__ im2, "
-          "long long N, double* __restrict__ gm)\n{\n";
+          "long long N, double* __restrict__ gm, double* __restrict__ sb)\n{\n";
     os << "  __shared__ double qx_gm[" << 4 * pr.npart * v.block << "];\n";
     const std::string gq_mark = "  //@GQ@\n";
     os << gq_mark;
@@ -1827,6 +1883,7 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     os << "  const long long pt = gid >> " << LB << ";\n";
     os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
     os << "  const long long ptc = pt < N ? pt : N - 1;\n";
+    os << "  const long long NL = N * " << G << ";\n  const long long gidc = gid < NL ? gid : NL - 1;\n";
     for (int p = 2; p < pr.npart; ++p)
       for (int mu = 0; mu < 4; ++mu) os << "  " << e.gmref(p, mu) << " = 0.0;\n";
     const std::string gq_zero_mark = "  //@GQZERO@\n";
@@ -1883,8 +1940,10 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     }
     all << ks;
     ++t;
+    }
   }
   if (count) *count = t;
+  if (sb_doubles) *sb_doubles = (1 << nloop) * sb_max * 8;
   if (stats) *stats = tot;
   return all.str();
 }

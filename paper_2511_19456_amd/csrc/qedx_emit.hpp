@@ -89,13 +89,17 @@ std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& 
 //   extern "C" __global__ void <kname>(const double* mom, long long N,
 //       double* amp /*[2H][N]*/, double* logm2, double* im2, double* gm /*[4 npart][N]*/)
 std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* st);
-// One kernel per photon partition, <kprefix>_<t>, t = 0..*count-1: the
-// partition's adjoint sweep for every configuration (seeds conj(A_h)/|M|^2
-// read from amp), adding its momentum gradient into gm:
+// Kernels <kprefix>_<t>, t = 0..*count-1, launched in order: per photon
+// partition the adjoint sweep for every configuration (seeds conj(A_h)/|M|^2
+// read from amp), adding its momentum gradient into gm.  A partition whose
+// dots factor into per-pattern leaf sums takes two kernels: the e-_out-side
+// walk, which stores that side's leaf sums to sb, then the e-_in-side walk,
+// which reads them; others take one.
 //   extern "C" __global__ void <kprefix>_<t>(const double* mom, const double* amp,
-//       const double* im2, long long N, double* gm)
+//       const double* im2, long long N, double* gm, double* sb)
+// sb: *sb_doubles doubles per lane of a launch (N x lanes per point).
 std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const std::string& kprefix, int* count,
-                                           EmitStats* st);
+                                           EmitStats* st, int* sb_doubles);
 
 // Device function text of one process body (used by the mixed batch module):
 //   __device__ double <fname>(const double* mom, long long N, long long pt,

@@ -180,6 +180,47 @@ struct Emitter {
     throw std::logic_error("shared e-_in side: unexpected node kind");
   }
 
+  // e-_in-side one-photon currents of a helicity-sum kernel (order flag
+  // 4096, with the shared e-_in side): every partition block that puts a
+  // photon first on the e-_in side rebuilt S(Q) eps-slash u for each of its
+  // polarisation states; they are computed once per point (and loop
+  // iteration) into per-lane LDS, [slot][8 words][block], and read there.
+  bool r1_cache = false;
+  std::map<int, int> r1_slot;  // S1 node -> LDS slot
+  std::string r1_ref(int slot, int w) const {
+    return "qx_r1[" + std::to_string((8 * slot + w) * v.block) + " + threadIdx.x]";
+  }
+  void r1_collect() {
+    for (size_t i = 0; i < d.nodes.size(); ++i) {
+      const Node& n = d.nodes[i];
+      if (n.kind == Kind::S1 && n.side == 0 && popc(n.mask) == 1 && !ein1((int)i) && !n.out.empty())
+        r1_slot[(int)i] = (int)r1_slot.size();
+    }
+  }
+  void emit_r1_cache() {
+    os << ind << "{\n";
+    std::string o = ind;
+    ind += "  ";
+    block_momenta();
+    std::fill(done.begin(), done.end(), 0);
+    kdone.clear();
+    qdone.clear();
+    const bool was = r1_cache;
+    r1_cache = false;  // compute them here
+    for (auto& kv : r1_slot) {
+      emit(kv.first);
+      for (int k = 0; k < 4; ++k)
+        os << ind << r1_ref(kv.second, 2 * k) << " = " << name(kv.first) << ".c[" << k << "].r; "
+           << r1_ref(kv.second, 2 * k + 1) << " = " << name(kv.first) << ".c[" << k << "].i;\n";
+    }
+    r1_cache = was;
+    std::fill(done.begin(), done.end(), 0);
+    kdone.clear();
+    qdone.clear();
+    ind = o;
+    os << ind << "}\n";
+  }
+
   // a device-function body of the persistent batch kernel: the cache is the
   // wave's own LDS region (BP = points per wave), tpt and sub are arguments,
   // and the wave synchronises only itself
@@ -283,6 +324,14 @@ struct Emitter {
     int c = producer(i);
     if (done[c]) return;
     const Node& n = d.nodes[c];
+    if (r1_cache && r1_slot.count(c)) {
+      os << ind << "const qx::sp4<" << T << "> n" << c << " = {{";
+      for (int k = 0; k < 4; ++k)
+        os << (k ? ", " : "") << "{" << r1_ref(r1_slot.at(c), 2 * k) << ", " << r1_ref(r1_slot.at(c), 2 * k + 1) << "}";
+      os << "}};\n";
+      done[c] = 1;
+      return;
+    }
     if (ein1(c)) {
       // built by the partner lane as its spin-0 twin
       const int t = twin(c);
@@ -789,6 +838,7 @@ struct Emitter {
     if (slot) {
       slot_loop(part);
     } else {
+      if (r1_cache) emit_r1_cache();
       for (uint32_t key : order) forward_block(key, part[key]);
     }
     // |A|^2, summed over the enumerated configurations (HelSum) or single
@@ -1576,6 +1626,12 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     e.coop = true;
     e.build_twins();
   }
+  if (v.order & 4096) {
+    if (!(v.order & 2048) || !(v.order & 4) || v.prec != PREC_F64)
+      throw std::invalid_argument("the e-_in-side current cache takes FP64 helicity sums with the shared e-_in side");
+    e.r1_cache = true;
+    e.r1_collect();
+  }
   e.mj_tab = kname + "_mjperm";
   const std::string mj_mark = "//@MJTAB@\n";
   if (e.mfma_join()) {
@@ -1623,6 +1679,7 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
       decl += "  __shared__ " + e.PT + " qx_pol[" + std::to_string(3 * d.proc.npart * v.block) + "];\n";
     }
     if (e.mfma_join()) decl += "  __shared__ double qx_mj[" + std::to_string(4 * 64 * Emitter::kMjStride) + "];\n";
+    if (e.r1_cache) decl += "  __shared__ double qx_r1[" + std::to_string(8 * e.r1_slot.size() * v.block) + "];\n";
     size_t at = src.find(lds_mark);
     src.replace(at, lds_mark.size(), decl);
     if (e.mfma_join()) src.replace(src.find(mj_mark), mj_mark.size(), e.mj_tables);

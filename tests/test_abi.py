@@ -155,8 +155,9 @@ def test_default_kernel_shapes():
         src = Q.emit_source(n, mode, prec, Q.make_variant(**kw) if kw else None)
         return src.splitlines()[0].split("generated by qedx: ")[1]
     # 4 photons, FP64 sum: e-_out spin on lanes, one block per partition
-    # (the two lanes share the e-_in side: order flag 2048)
-    assert tag(3, "sum", "fp64") == "nin1_nout3_p0_m0_e59_l4_o0_b256_s2_j1_r2052_w0"
+    # (the two lanes share the e-_in side, order flag 2048, and its one-photon
+    # currents are cached in LDS, 4096)
+    assert tag(3, "sum", "fp64") == "nin1_nout3_p0_m0_e59_l4_o0_b256_s2_j1_r6148_w0"
     # FP32C and the distributive rewrite keep both spins on lanes, shared block
     assert "_l5_o0_" in tag(3, "sum", "fp32c") and "_r0_" in tag(3, "sum", "fp32c")
     assert "_l5_o0_" in tag(3, "sum", "fp64", rewrite=1)

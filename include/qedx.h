@@ -86,11 +86,15 @@ typedef struct {
   int32_t block;
   int32_t split;
   int32_t min_waves;    /* minimum waves per SIMD the compiler must allow (0 = library default) */
-  int32_t order;        /* emission schedule flags (0 = library default).  Per-point FP64
+  int32_t order;        /* emission schedule flags (0 = library default).  Per-point
                            partition loops (8) may add the one-photon current cache: 256 =
                            2 lanes per point, 512 = 4 lanes per point, 1024 = cache the
                            e-_in side's currents only; qed_process_info reports the
-                           resulting lanes_per_point */
+                           resulting lanes_per_point.  Helicity sums with per-partition
+                           blocks (4) and the e-_out spin as their one lane bit may add
+                           2048 (the two lanes share the e-_in side, each building it for
+                           one e-_in spin) and, with it, 4096 (that side's one-photon
+                           currents cached in LDS) */
   int32_t use_defaults; /* nonzero: ignore the fields above and below */
   int32_t rewrite;      /* 0 = node reduction only (the paper's CDAG optimisation, App. C);
                            1 = node reduction followed by the distributive rewrite the paper

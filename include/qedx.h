@@ -185,11 +185,12 @@ qed_status qed_rambo(const qed_process* p, const double* uniforms, double sqrt_s
  * n <= 3: forward RAMBO, forward graph, adjoint graph and adjoint RAMBO in one
  * kernel; no workspace (workspace may be NULL).  n = 4: per chunk of points,
  * RAMBO into the workspace, one kernel storing every configuration's
- * amplitude A_h and 1/|M|^2 (the adjoint seeds conj(A_h)/|M|^2), one adjoint
- * kernel per photon partition, and the RAMBO adjoint.  The workspace is
+ * amplitude A_h and 1/|M|^2 (the adjoint seeds conj(A_h)/|M|^2), the adjoint
+ * kernels of the photon partitions (two per partition: the e-_out-side and
+ * the e-_in-side walk), and the RAMBO adjoint.  The workspace is
  * caller-owned device memory, 8-byte aligned, of workspace_bytes bytes: its
  * size sets the chunk (qed_eval_grad_workspace_size gives the size for the
- * largest chunk, about 3.5 KB per point at n = 4, at most 512 MB); less than
+ * largest chunk, about 2.5 KB per point at n = 4, at most 512 MB); less than
  * 64 points' worth (or N's, if smaller) is INVALID_ARG.  Calls that overlap
  * need workspaces of their own.  `hel` must be NULL.  UNSUPPORTED for
  * PER_POINT or FP32C processes and for n >= 5. */

@@ -995,7 +995,35 @@ struct Emitter {
   bool gm_in_lds = false;
   std::string gmref(int p, int mu) const {
     if (!gm_in_lds) return "gm" + std::to_string(p) + "_" + std::to_string(mu);
-    return "qx_gm[" + std::to_string((4 * p + mu) * v.block) + " + threadIdx.x]";
+    if (p < pr.i_eout) throw std::logic_error("gmref(): no gradient slot for an incoming particle");
+    return "qx_gm[" + std::to_string((4 * (p - pr.i_eout) + mu) * v.block) + " + threadIdx.x]";
+  }
+
+  // Polarisation-vector gradients of the walked side in per-lane LDS slots
+  // (ge_in_lds), allocated on first use; a polarisation whose gradient the
+  // block never touches gets no slot and no pol_vjp.
+  bool ge_in_lds = false;
+  const std::string ge_zero_mark = "//@GEZERO@\n";
+  std::map<int, int> ge_slot;
+  int ge_index(int x) {
+    auto it = ge_slot.find(x);
+    if (it != ge_slot.end()) return it->second;
+    int k = (int)ge_slot.size();
+    ge_slot[x] = k;
+    return k;
+  }
+  std::string geref(int slot, int c) const {
+    return "qx_ge[" + std::to_string((3 * slot + c) * v.block) + " + threadIdx.x]";
+  }
+  // vertex gradient with respect to the polarisation vector of node u
+  void emit_ge(const std::string& side, const std::string& w, const std::string& X, int u) {
+    if (!ge_in_lds) {
+      os << ind << "qx::v" << side << "_ge<double>(" << w << ", " << X << ", ge" << u << ");\n";
+      return;
+    }
+    const int k = ge_index(u);
+    os << ind << "{ qx::pol3<double> t = {0.0, 0.0, 0.0}; qx::v" << side << "_ge<double>(" << w << ", " << X
+       << ", t); " << geref(k, 0) << " += t.e1; " << geref(k, 1) << " += t.e2; " << geref(k, 2) << " += t.e3; }\n";
   }
 
   // Propagator-coefficient gradients accumulated per distinct propagator
@@ -1119,10 +1147,14 @@ struct Emitter {
         os << ind << "const qx::sp4<double> f" << c << " = qx::s" << side << "<double>(" << X << ", q);\n";
       if (factored && memB.count(c)) {
         // row leaf of a factored block: its adjoint is the row seed of its
-        // configurations, and it joins their row sum
+        // configurations; in the one-kernel sweep it also joins their row
+        // sum (the split e-_in-side kernel recomputes those sums itself)
         os << ind << "const qx::sp4<double> w" << c << " = T" << memB.at(c) << ";\n";
-        os << ind << "qx::add_to(SB" << memB.at(c) << ", f" << c << ");\n";
-        st.flops_per_point += n.kind == Kind::V ? 40 + 8 : 56 + 8;
+        if (grad_phase == 0) {
+          os << ind << "qx::add_to(SB" << memB.at(c) << ", f" << c << ");\n";
+          st.flops_per_point += 8;
+        }
+        st.flops_per_point += n.kind == Kind::V ? 40 : 56;
       } else {
         os << ind << "qx::sp4<double> w" << c << " = qx::zero4<double>();\n";
         st.flops_per_point += n.kind == Kind::V ? 40 : 56;
@@ -1131,7 +1163,7 @@ struct Emitter {
     }
     if (n.kind == Kind::V) {
       os << ind << "qx::add_to(w" << x << ", qx::v" << other << "<double>(" << wc << ", " << E << "));\n";
-      os << ind << "qx::v" << side << "_ge<double>(" << wc << ", " << X << ", ge" << producer(n.in[0]) << ");\n";
+      emit_ge(side, wc, X, producer(n.in[0]));
       st.flops_per_point += 40 + 48;
     } else {
       os << ind << "qx::add_to(w" << x << ", qx::s" << other << "<double>(" << wc << ", q));\n";
@@ -1268,6 +1300,7 @@ struct Emitter {
   void dist_adjoint_block(uint32_t key, const std::vector<int>& dk) {
     os << ind << "// adjoint (subset currents): photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << "\n";
     std::string outer = open_block();
+    flush_seeds();
     std::vector<int> pols;
     for (size_t i = 0; i < d.nodes.size(); ++i) {
       const Node& n = d.nodes[i];
@@ -1359,31 +1392,58 @@ struct Emitter {
   }
 
   // Split adjoint kernels (grad_phase): 0 = the whole partition sweep; 1 =
-  // the e-_out-side walk, storing that side's leaf sums per pattern to sb;
-  // 2 = the e-_in-side walk, with those sums loaded from sb.  Each of the
-  // two kernels holds only its own walk's state (the seeds are needed only
-  // before the walk of phase 1).  sb holds, per lane of the launch
-  // (NL = N x lanes) and loop iteration lp, 8 doubles per pattern:
-  // sb[((lp * npb + i) * 8 + w) * NL + gid].
+  // the e-_out-side walk; 2 = the e-_in-side walk.  Each of the two kernels
+  // holds only its own walk's state: the seeds of its side come from a
+  // forward walk of the other side's trie in a scope of its own (its leaf
+  // sums), so nothing passes between the two kernels but the momentum
+  // gradients they add.
   int grad_phase = 0;
-  std::string sb_ref(int i, int w) const {
-    return "sb[((lp * " + std::to_string(sb_npb) + "u + " + std::to_string(i) + "u) * 8u + " + std::to_string(w) +
-           "u) * NL + gidc]";
+  // statements defining the adjoint seeds c<a> (partition adjoint kernels),
+  // emitted by the block where it first needs them
+  std::string seed_code;
+  void flush_seeds() {
+    std::istringstream in(seed_code);
+    for (std::string line; std::getline(in, line);) os << ind << line << "\n";
+    seed_code.clear();
   }
-  int sb_npb = 0;
+
+  // forward walk of the leaves `leaves` (node -> pattern) in a scope of its
+  // own, summing them per pattern into <S><pattern>; its currents die with
+  // the scope (the adjoint walk recomputes what it needs)
+  void leaf_sums(const std::map<int, uint32_t>& leaves, const std::string& S, const std::set<uint32_t>& pats) {
+    for (uint32_t q : pats) os << ind << "qx::sp4<double> " << S << q << " = qx::zero4<double>();\n";
+    os << ind << "{\n";
+    std::string o = ind;
+    ind += "  ";
+    std::vector<char> done0 = done;
+    std::set<uint32_t> kdone0 = kdone;
+    std::set<std::pair<int, uint32_t>> qdone0 = qdone;
+    for (auto& kv : leaves) {
+      emit(kv.first);
+      os << ind << "qx::add_to(" << S << kv.second << ", " << name(kv.first) << ");\n";
+      st.flops_per_point += 8;
+    }
+    done = done0;
+    kdone = kdone0;
+    qdone = qdone0;
+    ind = o;
+    os << ind << "}\n";
+  }
 
   void grad_block(uint32_t key, const std::vector<int>& dk) {
     collect_block(dk);
     os << ind << "// adjoint: photons " << key << " | " << (((1u << pr.P) - 1) & ~key) << "\n";
     std::string outer = open_block();
-    // polarisation-gradient accumulators of this block
+    // polarisation-gradient accumulators of this block (registers, or LDS
+    // slots zeroed at the marker once the walk has allocated them)
     for (int x : blk) {
       const Node& n = d.nodes[x];
       if (n.kind == Kind::U && n.particle != pr.i_ein && n.particle != pr.i_eout) {
         emit(x);
-        os << ind << "qx::pol3<double> ge" << x << " = {0.0, 0.0, 0.0};\n";
+        if (!ge_in_lds) os << ind << "qx::pol3<double> ge" << x << " = {0.0, 0.0, 0.0};\n";
       }
     }
+    if (ge_in_lds) os << ge_zero_mark;
     leafJ.clear();
     for (int k : dk) leafJ.insert(producer(dot_ops(d.nodes[k]).first));
     factored = factor_block(dk);
@@ -1393,39 +1453,20 @@ struct Emitter {
       for (auto& kv : memJ) patJ.insert(kv.second);
     }
     if (factored && grad_phase == 2) {
-      // the e-_out side's leaf sums, from the phase-1 kernel
-      int i = 0;
-      for (uint32_t q : patB) {
-        os << ind << "const qx::sp4<double> SB" << q << " = {{";
-        for (int k = 0; k < 4; ++k) os << (k ? ", " : "") << "{" << sb_ref(i, 2 * k) << ", " << sb_ref(i, 2 * k + 1) << "}";
-        os << "}};\n";
-        ++i;
-      }
+      // the e-_out side's leaf sums, from a forward walk of the row trie
+      leaf_sums(memB, "SB", patB);
+      flush_seeds();
     } else if (factored) {
-      // column sums per pattern, from a forward walk of the column trie in a
-      // scope of its own (its currents die with it; the column sweep below
-      // recomputes them)
-      for (uint32_t q : patJ) os << ind << "qx::sp4<double> SJ" << q << " = qx::zero4<double>();\n";
-      os << ind << "{\n";
-      std::string o = ind;
-      ind += "  ";
-      std::vector<char> done0 = done;
-      std::set<uint32_t> kdone0 = kdone;
-      std::set<std::pair<int, uint32_t>> qdone0 = qdone;
-      for (int J : leafJ) {
-        emit(J);
-        os << ind << "qx::add_to(SJ" << memJ.at(J) << ", " << name(J) << ");\n";
-        st.flops_per_point += 8;
-      }
-      done = done0;
-      kdone = kdone0;
-      qdone = qdone0;
-      ind = o;
-      os << ind << "}\n";
-      // row seeds, and the row sums the row sweep accumulates
+      // column sums per pattern, from a forward walk of the column trie
+      leaf_sums(memJ, "SJ", patJ);
+      flush_seeds();
+      // row seeds, and (one-kernel sweep) the row sums the row sweep
+      // accumulates
       for (uint32_t q : patB) emit_seed("T" + std::to_string(q), q, "SJ", patJ);
-      for (uint32_t q : patB) os << ind << "qx::sp4<double> SB" << q << " = qx::zero4<double>();\n";
+      if (grad_phase == 0)
+        for (uint32_t q : patB) os << ind << "qx::sp4<double> SB" << q << " = qx::zero4<double>();\n";
     } else {
+      flush_seeds();
       for (int J : leafJ) {
         emit(J);
         os << ind << "qx::sp4<double> w" << J << " = qx::zero4<double>();\n";
@@ -1451,26 +1492,21 @@ struct Emitter {
           os << ind << "}\n";
         }
       }
-      if (pass == 0 && grad_phase == 1) {
-        // the e-_out side's leaf sums for the phase-2 kernel
-        int i = 0;
-        for (uint32_t q : patB) {
-          os << ind << "if (gid < NL) {";
-          for (int k = 0; k < 4; ++k)
-            os << " " << sb_ref(i, 2 * k) << " = SB" << q << ".c[" << k << "].r; " << sb_ref(i, 2 * k + 1) << " = SB" << q
-               << ".c[" << k << "].i;";
-          os << " }\n";
-          ++i;
-        }
-      }
     }
     // polarisation vectors -> photon momenta
     for (int x : blk) {
       const Node& n = d.nodes[x];
       if (n.kind == Kind::U && n.particle != pr.i_ein && n.particle != pr.i_eout && final_particle(n.particle)) {
+        std::string ge = "ge" + std::to_string(x);
+        if (ge_in_lds) {
+          auto it = ge_slot.find(x);
+          if (it == ge_slot.end()) continue;  // gradient never touched by this block
+          ge = "qx::pol3<double>{" + geref(it->second, 0) + ", " + geref(it->second, 1) + ", " +
+               geref(it->second, 2) + "}";
+        }
         std::string m = "m" + std::to_string(n.particle) + "_";
-        os << ind << "{ double g[3]; qx::pol_vjp(" << m << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", ge"
-           << x << ", g);\n";
+        os << ind << "{ double g[3]; qx::pol_vjp(" << m << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", " << ge
+           << ", g);\n";
         for (int mu = 1; mu < 4; ++mu)
           os << ind << "  " << gmref(n.particle, mu) << " += g[" << (mu - 1) << "];\n";
         os << ind << "}\n";
@@ -1886,7 +1922,7 @@ std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& k
 }
 
 std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const std::string& kprefix, int* count,
-                                           EmitStats* stats, int* sb_doubles) {
+                                           EmitStats* stats) {
   check_variant(d, v);
   if (v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4) || (v.order & (8 | 16)))
     throw std::invalid_argument("adjoint kernels take SUM, FP64, local blocks");
@@ -1904,26 +1940,25 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
   std::ostringstream all;
   EmitStats tot;
   int t = 0;
-  int sb_max = 0;
+  // per-lane LDS of one workgroup at one wave per SIMD (160 KB per CU)
+  const int64_t kLdsBytes = 160 * 1024;
   for (uint32_t key : order) {
     // factored partitions: two kernels (e-_out-side walk, e-_in-side walk)
-    int npb = 0;
+    bool split = false;
     if (!d.distributed) {
       Emitter pe(d, v);
       std::vector<int> ps = pe.sum_nodes();
       for (size_t a = 0; a < ps.size(); ++a) pe.acc_of_sum[ps[a]] = (int)a;
       pe.collect_block(part[key]);
-      if (pe.factor_block(part[key])) {
-        std::set<uint32_t> pb;
-        for (auto& kv : pe.memB) pb.insert(kv.second);
-        npb = (int)pb.size();
-      }
+      split = pe.factor_block(part[key]);
     }
-    sb_max = std::max(sb_max, npb);
-    for (int phase = npb ? 1 : 0; phase <= (npb ? 2 : 0); ++phase) {
+    for (int phase = split ? 1 : 0; phase <= (split ? 2 : 0); ++phase) {
+    // the e-_out-side walk keeps its polarisation gradients in LDS when they
+    // fit beside the momentum and propagator gradients
+    for (int ge_lds = phase == 1 ? 1 : 0; ge_lds >= 0; --ge_lds) {
     Emitter e(d, v);
     e.grad_phase = phase;
-    e.sb_npb = npb;
+    e.ge_in_lds = ge_lds != 0;
     e.mom_src = 0;       // momenta reloaded per block from the workspace
     e.gm_in_lds = true;  // gradient accumulators in per-lane LDS slots
     e.gq_in_lds = !d.distributed;  // propagator gradients per propagator, flushed once
@@ -1932,8 +1967,9 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     std::ostringstream& os = e.os;
     os << "extern \"C\" __global__ void __launch_bounds__(" << v.block << ")\n" << kprefix << "_" << t
        << "(const double* __restrict__ mom, const double* __restrict__ amp, const double* __restrict__ im2, "
-          "long long N, double* __restrict__ gm, double* __restrict__ sb)\n{\n";
-    os << "  __shared__ double qx_gm[" << 4 * pr.npart * v.block << "];\n";
+          "long long N, double* __restrict__ gm)\n{\n";
+    const int ngm = 4 * (pr.npart - pr.i_eout);
+    os << "  __shared__ double qx_gm[" << ngm * v.block << "];\n";
     const std::string gq_mark = "  //@GQ@\n";
     os << gq_mark;
     os << "  const long long gid = (long long)blockIdx.x * " << v.block << " + threadIdx.x;\n";
@@ -1941,7 +1977,7 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
     os << "  const long long ptc = pt < N ? pt : N - 1;\n";
     os << "  const long long NL = N * " << G << ";\n  const long long gidc = gid < NL ? gid : NL - 1;\n";
-    for (int p = 2; p < pr.npart; ++p)
+    for (int p = pr.i_eout; p < pr.npart; ++p)
       for (int mu = 0; mu < 4; ++mu) os << "  " << e.gmref(p, mu) << " = 0.0;\n";
     const std::string gq_zero_mark = "  //@GQZERO@\n";
     os << gq_zero_mark;
@@ -1950,11 +1986,16 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     os << "  #pragma unroll 1\n  for (unsigned lp = 0; lp < " << (1u << nloop) << "u; ++lp) {\n";
     os << "    const unsigned hc = hrt | " << Emitter::deposit("lp", v.loop_mask) << ";\n";
     e.ind = "    ";
-    // seeds: conj(A_h) / |M|^2 of this iteration's configurations
-    for (size_t a = 0; a < sums.size(); ++a) {
-      os << e.ind << "const unsigned h" << a << " = hc | " << d.nodes[sums[a]].cfg << "u;\n";
-      os << e.ind << "const qx::cx<double> c" << a << " = {amp[(2 * h" << a << ") * N + ptc] * iM2, -amp[(2 * h" << a
-         << " + 1) * N + ptc] * iM2};\n";
+    // seeds: conj(A_h) / |M|^2 of this iteration's configurations, loaded
+    // where the block first needs them (after its leaf-sum walk)
+    {
+      std::ostringstream sc;
+      for (size_t a = 0; a < sums.size(); ++a) {
+        sc << "const unsigned h" << a << " = hc | " << d.nodes[sums[a]].cfg << "u; ";
+        sc << "const qx::cx<double> c" << a << " = {amp[(2 * h" << a << ") * N + ptc] * iM2, -amp[(2 * h" << a
+           << " + 1) * N + ptc] * iM2};\n";
+      }
+      e.seed_code = sc.str();
     }
     if (d.distributed)
       e.dist_adjoint_block(key, part[key]);
@@ -1971,36 +2012,44 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
       e.ind = "  ";
       os << "  }\n";
     }
-    for (int p = 2; p < pr.npart; ++p)
+    for (int p = pr.i_eout; p < pr.npart; ++p)
       for (int mu = 0; mu < 4; ++mu) {
         os << "  double gm" << p << "_" << mu << " = " << e.gmref(p, mu) << ";\n";
         for (int o = 1; o < G; o <<= 1)
           os << "  gm" << p << "_" << mu << " += __shfl_xor(gm" << p << "_" << mu << ", " << o << ");\n";
       }
     os << "  if (pt < N && sub == 0u) {\n";
-    for (int p = 2; p < pr.npart; ++p)
+    for (int p = pr.i_eout; p < pr.npart; ++p)
       for (int mu = 0; mu < 4; ++mu)
         os << "    gm[" << (4 * p + mu) << " * N + pt] += gm" << p << "_" << mu << ";\n";
     os << "  }\n}\n";
+    const int ns = (int)e.gq_slot.size(), nge = (int)e.ge_slot.size();
+    if (ge_lds && (int64_t)(ngm + 5 * ns + 3 * nge) * v.block * 8 > kLdsBytes) continue;  // registers instead
     tot.flops_per_point += e.st.flops_per_point * (double)G * (double)(1 << nloop);
     std::string ks = os.str();
     {
-      const int ns = (int)e.gq_slot.size();
-      std::string decl, zero;
+      std::string decl, zero, gezero;
       if (ns > 0) {
         decl = "  __shared__ double qx_gq[" + std::to_string(5 * ns * v.block) + "];\n";
         for (int k = 0; k < ns; ++k)
           for (int c = 0; c < 5; ++c) zero += "  " + e.gqref(k, c) + " = 0.0;\n";
       }
+      if (nge > 0) {
+        decl += "  __shared__ double qx_ge[" + std::to_string(3 * nge * v.block) + "];\n";
+        for (int k = 0; k < nge; ++k)
+          for (int c = 0; c < 3; ++c) gezero += "        " + e.geref(k, c) + " = 0.0;\n";
+      }
       ks.replace(ks.find(gq_mark), gq_mark.size(), decl);
       ks.replace(ks.find(gq_zero_mark), gq_zero_mark.size(), zero);
+      if (e.ge_in_lds) ks.replace(ks.find(e.ge_zero_mark), e.ge_zero_mark.size(), gezero);
     }
     all << ks;
     ++t;
+    break;
+    }
     }
   }
   if (count) *count = t;
-  if (sb_doubles) *sb_doubles = (1 << nloop) * sb_max * 8;
   if (stats) *stats = tot;
   return all.str();
 }

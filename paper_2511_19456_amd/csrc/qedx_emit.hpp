@@ -92,14 +92,13 @@ std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& k
 // Kernels <kprefix>_<t>, t = 0..*count-1, launched in order: per photon
 // partition the adjoint sweep for every configuration (seeds conj(A_h)/|M|^2
 // read from amp), adding its momentum gradient into gm.  A partition whose
-// dots factor into per-pattern leaf sums takes two kernels: the e-_out-side
-// walk, which stores that side's leaf sums to sb, then the e-_in-side walk,
-// which reads them; others take one.
+// dots factor into per-pattern leaf sums takes two kernels, the e-_out-side
+// walk and the e-_in-side walk, each obtaining the other side's leaf sums by
+// a forward walk of its own; others take one.
 //   extern "C" __global__ void <kprefix>_<t>(const double* mom, const double* amp,
-//       const double* im2, long long N, double* gm, double* sb)
-// sb: *sb_doubles doubles per lane of a launch (N x lanes per point).
+//       const double* im2, long long N, double* gm)
 std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const std::string& kprefix, int* count,
-                                           EmitStats* st, int* sb_doubles);
+                                           EmitStats* st);
 
 // Device function text of one process body (used by the mixed batch module):
 //   __device__ double <fname>(const double* mom, long long N, long long pt,

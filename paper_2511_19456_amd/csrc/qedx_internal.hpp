@@ -34,7 +34,7 @@ struct qed_process {
   int grad_block = 256;
   int grad_lanes = 0;
   // split gradient (n = 4): kernels; the workspace is the caller's
-  int grad_split = 0, amp_lanes = 0, adj_lanes = 0, adj_sb = 0;
+  int grad_split = 0, amp_lanes = 0, adj_lanes = 0;
   hipFunction_t f_grambo = nullptr, f_gamp = nullptr, f_grvjp = nullptr;
   std::vector<hipFunction_t> f_gadj;
   std::string eval_src;

@@ -14,7 +14,6 @@ struct AuxInfo {
   int split = 0;                       // 1: split gradient kernels instead
   int n_adj = 0;                       // number of per-partition adjoint kernels
   int amp_lanes = 0, adj_lanes = 0;    // lanes per point of the amplitude / adjoint kernels
-  int adj_sb = 0;                      // doubles per adjoint lane passed between split adjoint kernels
 };
 
 // HIP source with

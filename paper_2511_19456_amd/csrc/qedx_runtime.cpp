@@ -573,7 +573,6 @@ static qed_status process_create(int nin, int n, qed_hel_mode mode, qed_precisio
     p->grad_split = ai.split;
     p->amp_lanes = ai.amp_lanes;
     p->adj_lanes = ai.adj_lanes;
-    p->adj_sb = ai.adj_sb;
     p->f_gadj.assign(ai.n_adj, nullptr);
   } catch (const std::exception& e) {
     return fail(QED_ERR_INVALID_ARG, std::string("aux emit: ") + e.what());
@@ -671,13 +670,12 @@ extern "C" qed_status qed_rambo(const qed_process* p, const double* uniforms, do
 }
 
 // Split gradient: bytes of workspace per point (momenta and momentum
-// gradient [4 npart] each, amplitudes [2 H], 1/|M|^2, the leaf sums passed
-// between the two kernels of a partition's adjoint) and the largest chunk of
-// points one pass takes (a power of two, at most 2^20 and 512 MB).
+// gradient [4 npart] each, amplitudes [2 H], 1/|M|^2) and the largest chunk
+// of points one pass takes (a power of two, at most 2^20 and 512 MB).
 static int64_t grad_ws_per_point(const qed_process* p) {
   const int npart = p->n + p->n_in + 2;
   const int64_t H = (int64_t)1 << npart;
-  return 8 * (2 * 4 * (int64_t)npart + 2 * H + 1 + (int64_t)p->adj_lanes * p->adj_sb);
+  return 8 * (2 * 4 * (int64_t)npart + 2 * H + 1);
 }
 
 static int64_t grad_max_chunk(const qed_process* p) {
@@ -707,7 +705,6 @@ static qed_status grad_split_chunks(const qed_process* p, const double* uniforms
     double* gm = mom + 4 * (int64_t)npart * cnt;
     double* amp = gm + 4 * (int64_t)npart * cnt;
     double* im2 = amp + 2 * H * cnt;
-    double* sb = im2 + cnt;
     const double* u = uniforms + off;
     double* lg = out_logm2 + off;
     double* gr = out_grad + off;
@@ -717,7 +714,7 @@ static qed_status grad_split_chunks(const qed_process* p, const double* uniforms
     void* a2[] = {(void*)&mom, (void*)&cnt, (void*)&amp, (void*)&lg, (void*)&im2, (void*)&gm};
     if ((st = launch(p->f_gamp, cnt * (int64_t)p->amp_lanes, 256, stream, a2))) return st;
     for (hipFunction_t f : p->f_gadj) {
-      void* a3[] = {(void*)&mom, (void*)&amp, (void*)&im2, (void*)&cnt, (void*)&gm, (void*)&sb};
+      void* a3[] = {(void*)&mom, (void*)&amp, (void*)&im2, (void*)&cnt, (void*)&gm};
       if ((st = launch(f, cnt * (int64_t)p->adj_lanes, 256, stream, a3))) return st;
     }
     void* a4[] = {(void*)&u, (void*)&ldu, (void*)&sqrt_s, (void*)&cnt, (void*)&gm, (void*)&gr, (void*)&ldu};

@@ -1026,7 +1026,8 @@ struct Emitter {
     }
     const int k = ge_index(u);
     os << ind << "{ qx::pol3<double> t = {0.0, 0.0, 0.0}; qx::v" << side << "_ge<double>(" << w << ", " << X
-       << ", t); " << geref(k, 0) << " += t.e1; " << geref(k, 1) << " += t.e2; " << geref(k, 2) << " += t.e3; }\n";
+       << ", t); " << addto(geref(k, 0), "t.e1") << " " << addto(geref(k, 1), "t.e2") << " " << addto(geref(k, 2), "t.e3")
+       << " }\n";
   }
 
   // Propagator-coefficient gradients accumulated per distinct propagator
@@ -1045,6 +1046,20 @@ struct Emitter {
   }
   std::string gqref(int slot, int c) const {
     return "qx_gq[" + std::to_string((5 * slot + c) * v.block) + " + threadIdx.x]";
+  }
+
+  // statement adding val (negated if neg) to the accumulator ref: +=, or,
+  // with lds_atomic set, for a per-lane LDS slot (qx_*) an LDS atomic add
+  // whose result is not read (ds_add_f64: no read-modify-write round trip
+  // for the wave to wait on; each slot belongs to one lane, so the adds keep
+  // program order).  Measured per kernel: faster in the e-_out-side walks,
+  // slower in the e-_in-side ones (whose repeated adds to one slot the
+  // compiler otherwise merges in registers).
+  bool lds_atomic = false;
+  std::string addto(const std::string& ref, const std::string& val, bool neg = false) const {
+    if (!lds_atomic || ref.compare(0, 3, "qx_") != 0) return ref + (neg ? " -= " : " += ") + val + ";";
+    return "__hip_atomic_fetch_add(&" + ref + ", " + (neg ? "-(" + val + ")" : val) +
+           ", __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);";
   }
 
   void collect_block(const std::vector<int>& dk) {
@@ -1090,12 +1105,12 @@ struct Emitter {
     os << ind << "  qx::prop_from_vjp(" << m << "0, " << m << "1, " << m << "2, " << m << "3, Kl0, Kl1, Kl2, Kl3, "
        << (side == 0 ? "1.0" : "-1.0") << ", 1.0, gq, gp, gK);\n";
     if (final_particle(pe))
-      for (int mu = 0; mu < 4; ++mu) os << ind << "  " << gmref(pe, mu) << " += gp[" << mu << "];\n";
+      for (int mu = 0; mu < 4; ++mu) os << ind << "  " << addto(gmref(pe, mu), "gp[" + std::to_string(mu) + "]") << "\n";
     for (int a = 0; a < pr.P; ++a)
       if (((mask >> a) & 1) && final_particle(pr.photon_particle[a]))
         for (int mu = 0; mu < 4; ++mu)
-          os << ind << "  " << gmref(pr.photon_particle[a], mu) << (pr.photon_sign[a] > 0 ? " += " : " -= ")
-             << "gK[" << mu << "];\n";
+          os << ind << "  "
+             << addto(gmref(pr.photon_particle[a], mu), "gK[" + std::to_string(mu) + "]", pr.photon_sign[a] < 0) << "\n";
     os << ind << "}\n";
   }
 
@@ -1172,8 +1187,13 @@ struct Emitter {
     }
     if (n.kind == Kind::V) {
       os << ind << "qx::add_to(w" << x << ", qx::v" << other << "<double>(" << wc << ", " << E << "));\n";
-      emit_ge(side, wc, X, producer(n.in[0]));
-      st.flops_per_point += 40 + 48;
+      st.flops_per_point += 40;
+      // polarisation gradient, for final-state photons only (the incoming
+      // photon's momentum is fixed)
+      if (final_particle(d.nodes[producer(n.in[0])].particle)) {
+        emit_ge(side, wc, X, producer(n.in[0]));
+        st.flops_per_point += 48;
+      }
     } else {
       os << ind << "qx::add_to(w" << x << ", qx::s" << other << "<double>(" << wc << ", q));\n";
       os << ind << "qx::propq<double> gq = {0.0, 0.0, 0.0, 0.0, 0.0};\n";
@@ -1181,7 +1201,7 @@ struct Emitter {
       if (gq_in_lds) {
         const int k = gq_index(n.side, n.mask);
         const char* f[5] = {"qm", "qp", "q1", "q2", "mm"};
-        for (int c = 0; c < 5; ++c) os << ind << gqref(k, c) << " += gq." << f[c] << ";\n";
+        for (int c = 0; c < 5; ++c) os << ind << addto(gqref(k, c), std::string("gq.") + f[c]) << "\n";
       } else {
         prop_grad_to_momenta(n.side, n.mask);
       }
@@ -1256,7 +1276,7 @@ struct Emitter {
           std::string m = "m" + std::to_string(pr.i_eout) + "_";
           os << ind << "{ double g[4]; qx::ubar_vjp(" << m << "0, " << m << "1, " << m << "2, " << m << "3, "
              << hel_expr(n) << ", 1.0, " << w << ", g);\n";
-          for (int mu = 0; mu < 4; ++mu) os << ind << "  " << gmref(pr.i_eout, mu) << " += g[" << mu << "];\n";
+          for (int mu = 0; mu < 4; ++mu) os << ind << "  " << addto(gmref(pr.i_eout, mu), "g[" + std::to_string(mu) + "]") << "\n";
           os << ind << "}\n";
         }
         return;
@@ -1338,7 +1358,7 @@ struct Emitter {
       std::string m = "m" + std::to_string(n.particle) + "_";
       os << ind << "{ double g[3]; qx::pol_vjp(" << m << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", ge" << u
          << ", g);\n";
-      for (int mu = 1; mu < 4; ++mu) os << ind << "  " << gmref(n.particle, mu) << " += g[" << (mu - 1) << "];\n";
+      for (int mu = 1; mu < 4; ++mu) os << ind << "  " << addto(gmref(n.particle, mu), "g[" + std::to_string(mu - 1) + "]") << "\n";
       os << ind << "}\n";
     }
     close_block(outer);
@@ -1497,7 +1517,7 @@ struct Emitter {
           std::string m = "m" + std::to_string(pr.i_eout) + "_";
           os << ind << "{ double g[4]; qx::ubar_vjp(" << m << "0, " << m << "1, " << m << "2, " << m << "3, "
              << hel_expr(n) << ", 1.0, w" << r << ", g);\n";
-          for (int mu = 0; mu < 4; ++mu) os << ind << "  " << gmref(pr.i_eout, mu) << " += g[" << mu << "];\n";
+          for (int mu = 0; mu < 4; ++mu) os << ind << "  " << addto(gmref(pr.i_eout, mu), "g[" + std::to_string(mu) + "]") << "\n";
           os << ind << "}\n";
         }
       }
@@ -1517,7 +1537,7 @@ struct Emitter {
         os << ind << "{ double g[3]; qx::pol_vjp(" << m << "1, " << m << "2, " << m << "3, " << hel_expr(n) << ", " << ge
            << ", g);\n";
         for (int mu = 1; mu < 4; ++mu)
-          os << ind << "  " << gmref(n.particle, mu) << " += g[" << (mu - 1) << "];\n";
+          os << ind << "  " << addto(gmref(n.particle, mu), "g[" + std::to_string(mu - 1) + "]") << "\n";
         os << ind << "}\n";
       }
     }
@@ -1968,6 +1988,7 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     Emitter e(d, v);
     e.grad_phase = phase;
     e.ge_in_lds = ge_lds != 0;
+    e.lds_atomic = phase == 1;
     e.mom_src = 0;       // momenta reloaded per block from the workspace
     e.gm_in_lds = true;  // gradient accumulators in per-lane LDS slots
     e.gq_in_lds = !d.distributed;  // propagator gradients per propagator, flushed once
@@ -1996,13 +2017,23 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     os << "    const unsigned hc = hrt | " << Emitter::deposit("lp", v.loop_mask) << ";\n";
     e.ind = "    ";
     // seeds: conj(A_h) / |M|^2 of this iteration's configurations, loaded
-    // where the block first needs them (after its leaf-sum walk)
+    // where the block first needs them (after its leaf-sum walk), 8 at a
+    // time behind an empty asm that takes all 16 values at once (otherwise,
+    // short of registers, the compiler waits for each load before issuing
+    // the next)
     {
       std::ostringstream sc;
-      for (size_t a = 0; a < sums.size(); ++a) {
-        sc << "const unsigned h" << a << " = hc | " << d.nodes[sums[a]].cfg << "u; ";
-        sc << "const qx::cx<double> c" << a << " = {amp[(2 * h" << a << ") * N + ptc] * iM2, -amp[(2 * h" << a
-           << " + 1) * N + ptc] * iM2};\n";
+      const size_t kBatch = 8;
+      for (size_t a0 = 0; a0 < sums.size(); a0 += kBatch) {
+        const size_t a1 = std::min(sums.size(), a0 + kBatch);
+        for (size_t a = a0; a < a1; ++a)
+          sc << "const unsigned h" << a << " = hc | " << d.nodes[sums[a]].cfg << "u; double cr" << a << " = amp[(2 * h"
+             << a << ") * N + ptc], ci" << a << " = amp[(2 * h" << a << " + 1) * N + ptc];\n";
+        sc << "asm volatile(\"\" :";
+        for (size_t a = a0; a < a1; ++a) sc << (a > a0 ? ", " : " ") << "\"+v\"(cr" << a << "), \"+v\"(ci" << a << ")";
+        sc << ");\n";
+        for (size_t a = a0; a < a1; ++a)
+          sc << "const qx::cx<double> c" << a << " = {cr" << a << " * iM2, -ci" << a << " * iM2};\n";
       }
       e.seed_code = sc.str();
     }
@@ -2027,10 +2058,15 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
         for (int o = 1; o < G; o <<= 1)
           os << "  gm" << p << "_" << mu << " += __shfl_xor(gm" << p << "_" << mu << ", " << o << ");\n";
       }
+    // all loads of gm before any store (the rows may alias for all the
+    // compiler knows, which would otherwise serialise each load-add-store)
     os << "  if (pt < N && sub == 0u) {\n";
     for (int p = pr.i_eout; p < pr.npart; ++p)
       for (int mu = 0; mu < 4; ++mu)
-        os << "    gm[" << (4 * p + mu) << " * N + pt] += gm" << p << "_" << mu << ";\n";
+        os << "    const double o" << p << "_" << mu << " = gm[" << (4 * p + mu) << " * N + pt];\n";
+    for (int p = pr.i_eout; p < pr.npart; ++p)
+      for (int mu = 0; mu < 4; ++mu)
+        os << "    gm[" << (4 * p + mu) << " * N + pt] = o" << p << "_" << mu << " + gm" << p << "_" << mu << ";\n";
     os << "  }\n}\n";
     const int ns = (int)e.gq_slot.size(), nge = (int)e.ge_slot.size();
     if (ge_lds && (int64_t)(ngm + 5 * ns + 3 * nge) * v.block * 8 > kLdsBytes) continue;  // registers instead

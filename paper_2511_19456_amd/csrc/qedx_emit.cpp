@@ -126,6 +126,7 @@ struct Emitter {
   // kTile streamed currents -- register pressure is then the accumulators,
   // one tile and one held current.
   std::map<int, std::string> alias;
+  bool batch_mom = false;  // block momenta loaded together (see block_momenta)
   bool amp_store = false;  // body() also stores every configuration's amplitude
   bool stage() const { return (v.order & 16) != 0; }
   int lds_slots = 0;
@@ -848,7 +849,12 @@ struct Emitter {
         // amp[2h][N], amp[2h+1][N].  Unguarded: a lane past the end computes
         // point N-1 (ptc) exactly as that point's own lane does and stores
         // the same bytes; a guard here measured 452 against 196 B of scratch
-        os << ind << "{ const unsigned hh = hc | " << d.nodes[sums[a]].cfg << "u; amp[(2 * hh) * N + ptc] = A" << a
+        // (shared e-_in side: lane 1's accumulators carry swapped e-_in labels)
+        std::string hh = "hc | " + std::to_string(d.nodes[sums[a]].cfg) + "u";
+        if (coop)
+          hh = "hc | (" + std::to_string(d.nodes[sums[a]].cfg) + "u ^ (((hc >> " + std::to_string(pr.i_eout) +
+               ") & 1u) << " + std::to_string(pr.i_ein) + "))";
+        os << ind << "{ const unsigned hh = " << hh << "; amp[(2 * hh) * N + ptc] = A" << a
            << ".r; amp[(2 * hh + 1) * N + ptc] = A" << a << ".i; }\n";
       }
       if (v.prec == PREC_F64) {
@@ -1547,7 +1553,22 @@ struct Emitter {
   // momenta for a partition-local block, opaque to the compiler
   void block_momenta() {
     if (mom_src == 2) return;  // momenta already in m<p>_<mu> of the enclosing scope
-    if (mom_src == 0) {
+    if (mom_src == 0 && batch_mom) {
+      // loaded together: an empty asm takes 16 values at a time (short of
+      // registers the compiler otherwise waits for each load in turn)
+      os << ind << "long long pq = ptc;\n" << ind << "asm volatile(\"\" : \"+v\"(pq));\n";
+      std::vector<std::string> ms;
+      for (int p = 0; p < pr.npart; ++p)
+        for (int mu = 0; mu < 4; ++mu) {
+          ms.push_back("m" + std::to_string(p) + "_" + std::to_string(mu));
+          os << ind << "double " << ms.back() << " = mom[" << (4 * p + mu) << " * N + pq];\n";
+        }
+      for (size_t i0 = 0; i0 < ms.size(); i0 += 16) {
+        os << ind << "asm volatile(\"\" :";
+        for (size_t i = i0; i < std::min(ms.size(), i0 + 16); ++i) os << (i > i0 ? ", " : " ") << "\"+v\"(" << ms[i] << ")";
+        os << ");\n";
+      }
+    } else if (mom_src == 0) {
       os << ind << "long long pq = ptc;\n" << ind << "asm volatile(\"\" : \"+v\"(pq));\n";
       load_momenta("mom", "N", "pq");
     } else {
@@ -1926,6 +1947,11 @@ std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& k
     throw std::invalid_argument("amplitude kernels take SUM, FP64, the node-reduced graph, no loop or LDS schedule");
   Emitter e(d, v);
   e.amp_store = true;
+  e.batch_mom = true;
+  if (v.order & 2048) {
+    e.coop = true;
+    e.build_twins();
+  }
   const Process& pr = d.proc;
   const int LB = popc(v.lane_mask), G = 1 << LB;
   std::ostringstream& os = e.os;

@@ -94,7 +94,8 @@ typedef struct {
                            blocks (4) and the e-_out spin as their one lane bit may add
                            2048 (the two lanes share the e-_in side, each building it for
                            one e-_in spin) and, with it, 4096 (that side's one-photon
-                           currents cached in LDS) */
+                           currents cached in LDS); per-partition blocks may add 8192
+                           (each block's momentum loads issued together) */
   int32_t use_defaults; /* nonzero: ignore the fields above and below */
   int32_t rewrite;      /* 0 = node reduction only (the paper's CDAG optimisation, App. C);
                            1 = node reduction followed by the distributive rewrite the paper

@@ -126,7 +126,7 @@ struct Emitter {
   // kTile streamed currents -- register pressure is then the accumulators,
   // one tile and one held current.
   std::map<int, std::string> alias;
-  bool batch_mom = false;  // block momenta loaded together (see block_momenta)
+  bool batch_mom = false;  // order flag 8192: block momenta loaded together (see block_momenta)
   bool amp_store = false;  // body() also stores every configuration's amplitude
   bool stage() const { return (v.order & 16) != 0; }
   int lds_slots = 0;
@@ -1639,12 +1639,13 @@ void check_variant(const Dag& d, const Variant& v) {
   if (((v.order & (256 | 512)) &&
        ((v.order & 256 && v.order & 512) || !(v.order & 8) || v.mode != HEL_PER_POINT || (v.order & 64) ||
         v.lane_mask || d.split < 2 || d.proc.P - d.split < 1 || d.distributed)) ||
-      ((v.order & 1024) && !(v.order & (256 | 512))) ||
+      ((v.order & 1024) && !(v.order & (256 | 512))) || ((v.order & 8192) && !(v.order & 4)) ||
       ((v.order & 2048) && (v.mode != HEL_SUM || v.lane_mask != (1u << d.proc.i_eout) ||
                             !((v.enum_mask >> d.proc.i_ein) & 1u) || (v.order & (8 | 16 | 128)) || d.distributed)))
     throw std::invalid_argument(
         "the one-photon current cache takes per-point partition loops with split >= 2; the shared e-_in side "
-        "takes helicity sums with the e-_out spin as the one lane bit and the e-_in spin in the graph");
+        "takes helicity sums with the e-_out spin as the one lane bit and the e-_in spin in the graph; batched "
+        "block momenta take per-partition blocks");
 }
 
 // The one-photon current cache of a variant for BP points per LDS region
@@ -1712,6 +1713,7 @@ std::string emit_eval_kernel(const Dag& d, const Variant& v, const std::string& 
     e.coop = true;
     e.build_twins();
   }
+  e.batch_mom = (v.order & 8192) != 0;
   if (v.order & 4096) {
     if (!(v.order & 2048) || !(v.order & 4) || v.prec != PREC_F64)
       throw std::invalid_argument("the e-_in-side current cache takes FP64 helicity sums with the shared e-_in side");
@@ -1947,7 +1949,7 @@ std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& k
     throw std::invalid_argument("amplitude kernels take SUM, FP64, the node-reduced graph, no loop or LDS schedule");
   Emitter e(d, v);
   e.amp_store = true;
-  e.batch_mom = true;
+  e.batch_mom = (v.order & 8192) != 0;
   if (v.order & 2048) {
     e.coop = true;
     e.build_twins();

@@ -316,8 +316,10 @@ static void default_variant(int n, int nin, qed_hel_mode mode, qed_precision pre
       if (P == 5 && prec == QED_FP64 && !rewrite) {
         v.lane_mask = 1u << i_eout;
         photons = all & ~v.lane_mask & ~1u;
-        // shared e-_in side: 5.16 against 5.23 ms on 2^18 points
-        v.order |= 2048;
+        // shared e-_in side: 5.16 against 5.23 ms on 2^18 points; each
+        // block's momentum loads issued together: 5.09 against 5.14 ms (at
+        // 4 photons the same measured slower, 1.65 against 1.62 ms)
+        v.order |= 2048 | 8192;
       }
       uint32_t e = (v.lane_mask & 1u) ? 0u : 1u;
       int k = 0;

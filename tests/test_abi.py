@@ -164,7 +164,7 @@ def test_default_kernel_shapes():
     # an explicit coverage keeps the shared block unless an order is given
     assert "_l7_o0_" in tag(3, "sum", "fp64", lane_bits=7) and "_r0_" in tag(3, "sum", "fp64", lane_bits=7)
     # 5 photons, FP64 sum: e-_in spin and 3 photons in the graph, 2 looped
-    assert tag(4, "sum", "fp64") == "nin1_nout4_p0_m0_e27_l4_o96_b256_s2_j1_r2052_w0"
+    assert tag(4, "sum", "fp64") == "nin1_nout4_p0_m0_e27_l4_o96_b256_s2_j1_r10244_w0"
     # per point: join split ceil(P/2) for 5 and 7 photons, slot loop with the
     # one-photon current cache (2 lanes and the e-_in side at 5 photons, 4
     # lanes and both sides at 6 and 7; FP64 and FP32C alike)

@@ -845,17 +845,10 @@ struct Emitter {
     // |A|^2, summed over the enumerated configurations (HelSum) or single
     for (size_t a = 0; a < sums.size(); ++a) {
       if (amp_store) {
-        // amplitude of configuration hc | (this Sum's enumerated bits) to
-        // amp[2h][N], amp[2h+1][N].  Unguarded: a lane past the end computes
-        // point N-1 (ptc) exactly as that point's own lane does and stores
-        // the same bytes; a guard here measured 452 against 196 B of scratch
-        // (shared e-_in side: lane 1's accumulators carry swapped e-_in labels)
-        std::string hh = "hc | " + std::to_string(d.nodes[sums[a]].cfg) + "u";
-        if (coop)
-          hh = "hc | (" + std::to_string(d.nodes[sums[a]].cfg) + "u ^ (((hc >> " + std::to_string(pr.i_eout) +
-               ") & 1u) << " + std::to_string(pr.i_ein) + "))";
-        os << ind << "{ const unsigned hh = " << hh << "; amp[(2 * hh) * N + ptc] = A" << a
-           << ".r; amp[(2 * hh + 1) * N + ptc] = A" << a << ".i; }\n";
+        // staged in per-lane LDS (qx_as) and stored below: stores with
+        // their 64-bit addresses held while the accumulators are live spilled
+        os << ind << "qx_as[" << (2 * a) * v.block << " + threadIdx.x] = A" << a << ".r; qx_as[" << (2 * a + 1) * v.block
+           << " + threadIdx.x] = A" << a << ".i;\n";
       }
       if (v.prec == PREC_F64) {
         os << ind << "acc += A" << a << ".r * A" << a << ".r + A" << a << ".i * A" << a << ".i;\n";
@@ -874,6 +867,22 @@ struct Emitter {
         os << " }\n";
       }
       st.flops_per_point += 4;
+    }
+    if (amp_store) {
+      // amplitude of configuration hc | (the Sum's enumerated bits) to
+      // amp[2h][N], amp[2h+1][N] (shared e-_in side: lane 1's accumulators
+      // carry swapped e-_in labels).  Unguarded: a lane past the end computes
+      // point N-1 (ptc) exactly as that point's own lane does and stores the
+      // same bytes.
+      os << ind << "{\n" << ind << "  const unsigned qx_cf[" << sums.size() << "] = {";
+      for (size_t a = 0; a < sums.size(); ++a) os << (a ? ", " : "") << d.nodes[sums[a]].cfg << "u";
+      os << "};\n";
+      std::string flip = coop ? " ^ (((hc >> " + std::to_string(pr.i_eout) + ") & 1u) << " + std::to_string(pr.i_ein) + ")" : "";
+      os << ind << "  #pragma unroll 4\n" << ind << "  for (int a = 0; a < " << sums.size() << "; ++a) {\n";
+      os << ind << "    const unsigned hh = hc | (qx_cf[a]" << flip << ");\n";
+      os << ind << "    amp[(2 * hh) * N + ptc] = qx_as[2 * a * " << v.block << " + threadIdx.x];\n";
+      os << ind << "    amp[(2 * hh + 1) * N + ptc] = qx_as[(2 * a + 1) * " << v.block << " + threadIdx.x];\n";
+      os << ind << "  }\n" << ind << "}\n";
     }
   }
 
@@ -1959,16 +1968,17 @@ std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& k
   std::ostringstream& os = e.os;
   os << "extern \"C\" __global__ void __launch_bounds__(" << v.block << ")\n" << kname
      << "(const double* __restrict__ mom, long long N, double* __restrict__ amp, double* __restrict__ logm2, "
-        "double* __restrict__ im2, double* __restrict__ gm)\n{\n";
+        "double* __restrict__ im2)\n{\n";
   os << "  const long long gid = (long long)blockIdx.x * " << v.block << " + threadIdx.x;\n";
   os << "  const long long pt = gid >> " << LB << ";\n";
   os << "  const unsigned sub = (unsigned)(gid & " << (G - 1) << ");\n";
   os << "  const long long ptc = pt < N ? pt : N - 1;\n";
+  {
+    // per-lane staging of one iteration's amplitudes
+    Emitter probe(d, v);
+    os << "  __shared__ double qx_as[" << 2 * probe.sum_nodes().size() * v.block << "];\n";
+  }
   if (!e.local()) e.load_momenta("mom", "N", "ptc");
-  os << "  if (pt < N && sub == 0u) {\n";
-  for (int p = 2; p < pr.npart; ++p)
-    for (int mu = 0; mu < 4; ++mu) os << "    gm[" << (4 * p + mu) << " * N + pt] = 0.0;\n";
-  os << "  }\n";
   os << "  double acc = 0.0;\n";
   e.lane_work(Emitter::deposit("sub", v.lane_mask));
   for (int o = 1; o < G; o <<= 1) os << "  acc += __shfl_xor(acc, " << o << ");\n";

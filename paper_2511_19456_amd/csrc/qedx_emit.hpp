@@ -84,10 +84,9 @@ std::string emit_grad_kernel(const Dag& d, const Variant& v, const std::string& 
 
 // Split gradient (SUM, FP64), for processes whose fused gradient kernel would
 // not fit the register file.  The amplitude kernel stores every
-// configuration's amplitude, log |M|^2 and 1/|M|^2, and zeroes the momentum
-// gradient rows of the final-state particles:
+// configuration's amplitude, log |M|^2 and 1/|M|^2:
 //   extern "C" __global__ void <kname>(const double* mom, long long N,
-//       double* amp /*[2H][N]*/, double* logm2, double* im2, double* gm /*[4 npart][N]*/)
+//       double* amp /*[2H][N]*/, double* logm2, double* im2)
 std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& kname, EmitStats* st);
 // Kernels <kprefix>_<t>, t = 0..*count-1, launched in order: per photon
 // partition the adjoint sweep for every configuration (seeds conj(A_h)/|M|^2

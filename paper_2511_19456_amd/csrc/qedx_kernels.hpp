@@ -23,8 +23,9 @@ struct AuxInfo {
 //  - n <= 3, fused: qedx_grad_n<n>(const double* u, double sqrt_s, long long N,
 //      double* logm2, double* grad);
 //  - n = 4, split over a caller workspace (the fused kernel spills heavily):
-//      qedx_grambo_n<n>(u, ldu, sqrt_s, N, mom)  RAMBO into the workspace,
-//      qedx_gamp_n<n>(mom, N, amp, logm2, im2, gm)  amplitudes of every configuration,
+//      qedx_grambo_n<n>(u, ldu, sqrt_s, N, mom, gm)  RAMBO into the workspace,
+//          the final-state momentum-gradient rows of gm zeroed,
+//      qedx_gamp_n<n>(mom, N, amp, logm2, im2)  amplitudes of every configuration,
 //      qedx_gadj_n<n>_<t>(mom, amp, im2, N, gm)  adjoint of photon partition t,
 //      qedx_grvjp_n<n>(u, ldu, sqrt_s, N, gm, grad, ldg)  RAMBO adjoint.
 // n >= 5 has RAMBO only (its split gradient module takes tens of minutes of

@@ -711,9 +711,9 @@ static qed_status grad_split_chunks(const qed_process* p, const double* uniforms
     double* lg = out_logm2 + off;
     double* gr = out_grad + off;
     qed_status st;
-    void* a1[] = {(void*)&u, (void*)&ldu, (void*)&sqrt_s, (void*)&cnt, (void*)&mom};
+    void* a1[] = {(void*)&u, (void*)&ldu, (void*)&sqrt_s, (void*)&cnt, (void*)&mom, (void*)&gm};
     if ((st = launch(p->f_grambo, cnt, 256, stream, a1))) return st;
-    void* a2[] = {(void*)&mom, (void*)&cnt, (void*)&amp, (void*)&lg, (void*)&im2, (void*)&gm};
+    void* a2[] = {(void*)&mom, (void*)&cnt, (void*)&amp, (void*)&lg, (void*)&im2};
     if ((st = launch(p->f_gamp, cnt * (int64_t)p->amp_lanes, 256, stream, a2))) return st;
     for (hipFunction_t f : p->f_gadj) {
       void* a3[] = {(void*)&mom, (void*)&amp, (void*)&im2, (void*)&cnt, (void*)&gm};

@@ -1423,8 +1423,9 @@ struct Emitter {
 
   // sum over the configurations a in `pat` of c_a times the patterns' sums
   // S<q> of every pattern q containing a
-  void emit_seed(const std::string& out, uint32_t pat, const std::string& S, const std::set<uint32_t>& pats) {
-    os << ind << "qx::sp4<double> " << out << " = qx::zero4<double>();\n";
+  void emit_seed(const std::string& out, uint32_t pat, const std::string& S, const std::set<uint32_t>& pats,
+                 bool declare = true) {
+    if (declare) os << ind << "qx::sp4<double> " << out << " = qx::zero4<double>();\n";
     for (int a = 0; a < 32; ++a) {
       if (!((pat >> a) & 1)) continue;
       for (uint32_t q : pats)
@@ -1442,6 +1443,12 @@ struct Emitter {
   // sums), so nothing passes between the two kernels but the momentum
   // gradients they add.
   int grad_phase = 0;
+  // Split kernels whose walked side has no looped photon: the walk's forward
+  // currents are the same in every loop iteration and its adjoints are
+  // linear in the seeds, so the seeds are summed over the iterations
+  // (merge_part 1, inside the loop: the other side's leaf sums and the seed
+  // sums) and the side is walked once (merge_part 2, after the loop).
+  int merge_part = 0;
   // statements defining the adjoint seeds c<a> (partition adjoint kernels),
   // emitted by the block where it first needs them
   std::string seed_code;
@@ -1484,10 +1491,10 @@ struct Emitter {
       const Node& n = d.nodes[x];
       if (n.kind == Kind::U && n.particle != pr.i_ein && n.particle != pr.i_eout) {
         emit(x);
-        if (!ge_in_lds) os << ind << "qx::pol3<double> ge" << x << " = {0.0, 0.0, 0.0};\n";
+        if (!ge_in_lds && merge_part != 1) os << ind << "qx::pol3<double> ge" << x << " = {0.0, 0.0, 0.0};\n";
       }
     }
-    if (ge_in_lds) os << ge_zero_mark;
+    if (ge_in_lds && merge_part != 1) os << ge_zero_mark;
     leafJ.clear();
     for (int k : dk) leafJ.insert(producer(dot_ops(d.nodes[k]).first));
     factored = factor_block(dk);
@@ -1496,7 +1503,23 @@ struct Emitter {
       for (auto& kv : memB) patB.insert(kv.second);
       for (auto& kv : memJ) patJ.insert(kv.second);
     }
-    if (factored && grad_phase == 2) {
+    if (merge_part == 1) {
+      // the other side's leaf sums and this iteration's share of the seeds
+      if (grad_phase == 2) {
+        leaf_sums(memB, "SB", patB);
+        flush_seeds();
+        for (uint32_t q : patJ) emit_seed("W" + std::to_string(q), q, "SB", patB, false);
+      } else {
+        leaf_sums(memJ, "SJ", patJ);
+        flush_seeds();
+        for (uint32_t q : patB) emit_seed("T" + std::to_string(q), q, "SJ", patJ, false);
+      }
+      close_block(outer);
+      return;
+    }
+    if (merge_part == 2) {
+      // seeds summed over the loop (declared by the kernel)
+    } else if (factored && grad_phase == 2) {
       // the e-_out side's leaf sums, from a forward walk of the row trie
       leaf_sums(memB, "SB", patB);
       flush_seeds();
@@ -1520,7 +1543,7 @@ struct Emitter {
     for (int pass = 0; pass < 2; ++pass) {
       if ((grad_phase == 1 && pass == 1) || (grad_phase == 2 && pass == 0)) continue;
       int root_particle = pass == 0 ? pr.i_eout : pr.i_ein;
-      if (pass == 1 && factored)
+      if (pass == 1 && factored && merge_part != 2)
         for (uint32_t q : patJ) emit_seed("W" + std::to_string(q), q, "SB", patB);
       for (int r : blk) {
         const Node& n = d.nodes[r];
@@ -2051,6 +2074,25 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     os << gq_zero_mark;
     os << "  const double iM2 = im2[ptc];\n";
     os << "  const unsigned hrt = " << Emitter::deposit("sub", v.lane_mask) << ";\n";
+    // merge: the walked side (phase 1: e-_out, phase 2: e-_in) holds no
+    // looped photon
+    uint32_t in_side = 0;
+    for (int a = 0; a < pr.P; ++a)
+      if ((key >> a) & 1) in_side |= 1u << pr.photon_particle[a];
+    const uint32_t photons_all = ((1u << pr.npart) - 1) & ~(1u << pr.i_ein) & ~(1u << pr.i_eout);
+    const uint32_t walked = phase == 1 ? (photons_all & ~in_side) : phase == 2 ? in_side : photons_all;
+    const bool merge = split && nloop > 0 && (v.loop_mask & walked) == 0;
+    if (merge) {
+      Emitter pm(d, v);
+      std::vector<int> ps = pm.sum_nodes();
+      for (size_t a = 0; a < ps.size(); ++a) pm.acc_of_sum[ps[a]] = (int)a;
+      pm.collect_block(part[key]);
+      pm.factor_block(part[key]);
+      std::set<uint32_t> pats;
+      for (auto& kv : (phase == 1 ? pm.memB : pm.memJ)) pats.insert(kv.second);
+      for (uint32_t q : pats)
+        os << "  qx::sp4<double> " << (phase == 1 ? "T" : "W") << q << " = qx::zero4<double>();\n";
+    }
     os << "  #pragma unroll 1\n  for (unsigned lp = 0; lp < " << (1u << nloop) << "u; ++lp) {\n";
     os << "    const unsigned hc = hrt | " << Emitter::deposit("lp", v.loop_mask) << ";\n";
     e.ind = "    ";
@@ -2077,10 +2119,21 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     }
     if (d.distributed)
       e.dist_adjoint_block(key, part[key]);
-    else
+    else {
+      e.merge_part = merge ? 1 : 0;
       e.grad_block(key, part[key]);
+    }
     e.ind = "  ";
     os << "  }\n";
+    if (merge) {
+      os << "  {\n    const unsigned hc = hrt;\n";
+      e.ind = "    ";
+      e.merge_part = 2;
+      e.grad_block(key, part[key]);
+      e.merge_part = 0;
+      e.ind = "  ";
+      os << "  }\n";
+    }
     if (!e.gq_slot.empty()) {
       // propagator gradients of every iteration -> momentum gradients
       os << "  {\n";

@@ -35,8 +35,19 @@ extern "C" {
  * buffers. */
 qed_status qed_pipe_probe(int kind, int64_t blocks, int64_t iters, int64_t iters2, double m, double c,
                           const double* a, const double* b, double* out, double* out2, void* stream);
-/* Compile the probe's code object into the cache (no GPU). */
+/* Compile the probe's code objects (this one and the reciprocal probe's)
+ * into the cache (no GPU). */
 qed_status qed_pipe_probe_prebuild(double* compile_ms);
+
+/* Reciprocal probe (test tool): r[i] = qx::rcp(x[i]) and q[i] =
+ * qx::rsqrt(|x[i]|) for i < n, computed by the device functions the
+ * generated kernels use for propagator denominators, spinor normalisations
+ * and polarisation vectors (the hardware estimates refined by two
+ * Newton-Raphson steps).  x, r, q: device buffers of n doubles owned by the
+ * caller; x nonzero and well inside the normal range.  Enqueued on stream
+ * (hipStream_t, may be NULL).  Errors: INVALID_ARG for n outside 1..2^30
+ * or a missing buffer. */
+qed_status qed_recip_probe(const double* x, int64_t n, double* r, double* q, void* stream);
 
 #ifdef __cplusplus
 }

@@ -98,6 +98,7 @@ PROBE_SIGNATURES = {
     "qed_pipe_probe": (c_int, [c_int, c_int64, c_int64, c_int64, c_double, c_double, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p]),
     "qed_pipe_probe_prebuild": (c_int, [ctypes.POINTER(c_double)]),
+    "qed_recip_probe": (c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
 }
 
 _lib = None
@@ -126,7 +127,7 @@ def lib():
 
 
 def probe_lib():
-    """libqedx_probe.so (FP64 pipe probe); it reports errors through libqedx's
+    """libqedx_probe.so (FP64 pipe probe, reciprocal probe); it reports errors through libqedx.s
     qed_last_error."""
     global _probe
     if _probe is None:

@@ -15,6 +15,7 @@
 #include <string>
 
 #include "../../include/qedx_probe.h"
+#include "qedx_emit.hpp"
 #include "qedx_internal.hpp"
 
 using namespace qedx_rt;
@@ -97,8 +98,20 @@ extern "C" __global__ __launch_bounds__(256) void qedx_probe_mixed(long long ite
 }
 )HIP";
 
+// the device header's reciprocal and reciprocal square root, lane by lane
+const char* kRecipKernel = R"HIP(
+extern "C" __global__ __launch_bounds__(256) void qedx_probe_recip(const double* __restrict__ x, long long n,
+                                                                    double* __restrict__ r, double* __restrict__ q) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double v = x[i];
+  r[i] = qx::rcp(v);
+  q[i] = qx::rsqrt(v < 0.0 ? -v : v);
+}
+)HIP";
+
 std::mutex g_mu;
-std::map<int, hipModule_t> g_mod;
+std::map<int, hipModule_t> g_mod, g_rmod;
 
 qed_status probe_code(std::string& co, double* ms) {
   KernelMeta meta;
@@ -109,11 +122,53 @@ qed_status probe_code(std::string& co, double* ms) {
   return s;
 }
 
+qed_status recip_code(std::string& co, double* ms) {
+  KernelMeta meta;
+  bool hit = false;
+  double t = 0;
+  qed_status s = get_code_object("probe_recip", "#include <hip/hip_runtime.h>\n" + qedx::device_header_text() + kRecipKernel,
+                                 co, meta, hit, t);
+  if (ms) *ms = t;
+  return s;
+}
+
 }  // namespace
 
 extern "C" qed_status qed_pipe_probe_prebuild(double* compile_ms) {
   std::string co;
-  return probe_code(co, compile_ms);
+  double t1 = 0, t2 = 0;
+  qed_status s = probe_code(co, &t1);
+  if (!s) s = recip_code(co, &t2);
+  if (compile_ms) *compile_ms = t1 + t2;
+  return s;
+}
+
+extern "C" qed_status qed_recip_probe(const double* x, int64_t n, double* r, double* q, void* stream) {
+  if (n < 1 || n > ((int64_t)1 << 30)) return fail(QED_ERR_INVALID_ARG, "n must be in 1..2^30");
+  if (!x || !r || !q) return fail(QED_ERR_INVALID_ARG, "missing buffer");
+  int dev = 0;
+  PROBE_HIPCHK(hipGetDevice(&dev));
+  hipModule_t mod = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_rmod.find(dev);
+    if (it == g_rmod.end()) {
+      std::string co;
+      qed_status s = recip_code(co, nullptr);
+      if (s) return s;
+      PROBE_HIPCHK(hipModuleLoadData(&mod, co.data()));
+      g_rmod[dev] = mod;
+    } else {
+      mod = it->second;
+    }
+  }
+  hipFunction_t f = nullptr;
+  PROBE_HIPCHK(hipModuleGetFunction(&f, mod, "qedx_probe_recip"));
+  long long nn = (long long)n;
+  void* args[] = {(void*)&x, (void*)&nn, (void*)&r, (void*)&q};
+  PROBE_HIPCHK(hipModuleLaunchKernel(f, (unsigned)((n + 255) / 256), 1, 1, 256, 1, 1, 0, (hipStream_t)stream, args,
+                                     nullptr));
+  return QED_OK;
 }
 
 extern "C" qed_status qed_pipe_probe(int kind, int64_t blocks, int64_t iters, int64_t iters2, double m, double c,

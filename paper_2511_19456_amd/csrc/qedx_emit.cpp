@@ -2011,8 +2011,33 @@ std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& k
   return os.str();
 }
 
+std::vector<std::pair<uint32_t, int>> adjoint_walks(const Dag& d, const Variant& v) {
+  std::map<uint32_t, std::vector<int>> part;
+  std::vector<uint32_t> order;
+  Emitter probe(d, v);
+  probe.partitions(part, order);
+  std::vector<std::pair<uint32_t, int>> w;
+  for (uint32_t key : order) {
+    bool split = false;
+    if (!d.distributed) {
+      Emitter pe(d, v);
+      std::vector<int> ps = pe.sum_nodes();
+      for (size_t a = 0; a < ps.size(); ++a) pe.acc_of_sum[ps[a]] = (int)a;
+      pe.collect_block(part[key]);
+      split = pe.factor_block(part[key]);
+    }
+    if (split) {
+      w.push_back({key, 1});
+      w.push_back({key, 2});
+    } else {
+      w.push_back({key, 0});
+    }
+  }
+  return w;
+}
+
 std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const std::string& kprefix, int* count,
-                                           EmitStats* stats) {
+                                           EmitStats* stats, uint32_t only_key, int only_phase, int t0) {
   check_variant(d, v);
   if (v.mode != HEL_SUM || v.prec != PREC_F64 || !(v.order & 4) || (v.order & (8 | 16)))
     throw std::invalid_argument("adjoint kernels take SUM, FP64, local blocks");
@@ -2029,10 +2054,11 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
   }
   std::ostringstream all;
   EmitStats tot;
-  int t = 0;
+  int t = t0;
   // per-lane LDS of one workgroup at one wave per SIMD (160 KB per CU)
   const int64_t kLdsBytes = 160 * 1024;
   for (uint32_t key : order) {
+    if (only_key != ~0u && key != only_key) continue;
     // factored partitions: two kernels (e-_out-side walk, e-_in-side walk)
     bool split = false;
     if (!d.distributed) {
@@ -2043,6 +2069,7 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
       split = pe.factor_block(part[key]);
     }
     for (int phase = split ? 1 : 0; phase <= (split ? 2 : 0); ++phase) {
+    if (only_phase >= 0 && phase != only_phase) continue;
     // the split walks keep their polarisation gradients in LDS when they fit
     // beside the momentum and propagator gradients
     for (int ge_lds = phase >= 1 ? 1 : 0; ge_lds >= 0; --ge_lds) {
@@ -2185,7 +2212,7 @@ std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const
     }
     }
   }
-  if (count) *count = t;
+  if (count) *count = t - t0;
   if (stats) *stats = tot;
   return all.str();
 }

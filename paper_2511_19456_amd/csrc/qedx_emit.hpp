@@ -3,6 +3,8 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "qedx_dag.hpp"
 
@@ -96,8 +98,14 @@ std::string emit_amp_kernel(const Dag& d, const Variant& v, const std::string& k
 // a forward walk of its own; others take one.
 //   extern "C" __global__ void <kprefix>_<t>(const double* mom, const double* amp,
 //       const double* im2, long long N, double* gm)
+// Only the kernels of partition only_key (~0u: all) and walk only_phase
+// (-1: all; 0 = the one-kernel sweep, 1 = e-_out side, 2 = e-_in side) are
+// emitted, numbered from t0; *count is the number emitted.
 std::string emit_partition_adjoint_kernels(const Dag& d, const Variant& v, const std::string& kprefix, int* count,
-                                           EmitStats* st);
+                                           EmitStats* st, uint32_t only_key = ~0u, int only_phase = -1, int t0 = 0);
+// The (partition, walk) pairs of the adjoint kernels of (d, v) in launch
+// order: (key, 1) and (key, 2) for a factored partition, (key, 0) otherwise.
+std::vector<std::pair<uint32_t, int>> adjoint_walks(const Dag& d, const Variant& v);
 
 // Device function text of one process body (used by the mixed batch module):
 //   __device__ double <fname>(const double* mom, long long N, long long pt,
